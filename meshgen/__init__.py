@@ -1,0 +1,293 @@
+"""Seeded synthetic triangle meshes for the meshlet-connectivity codec.
+
+This module only produces input connectivity (``uint32[T, 3]`` CCW triangle
+lists plus a vertex count).  It holds none of the codec's arithmetic: no
+meshlet building, no strips, no bit packing, no decoding.  Both the oracle
+side (tests) and the product side (bench) draw their inputs from here.
+
+The paper evaluates on six scanned meshes that are not available here; these
+generators stand in for them with the shapes of its workloads (regular grids,
+subdivided spheres, irregular Delaunay patches), as listed per workload below.
+
+Every generator takes a ``numpy.random.Generator``; ``rng_for(workload, i)``
+builds the one used for mesh ``i`` of a workload, so each mesh is reproducible
+on its own.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from functools import lru_cache
+
+import numpy as np
+
+SEED_ROOT = (2404, 6359)
+
+
+def rng_for(workload: int, i: int = 0) -> np.random.Generator:
+    """Generator for mesh ``i`` of workload ``workload`` (1..5)."""
+    return np.random.default_rng(np.random.SeedSequence([*SEED_ROOT, workload, i]))
+
+
+@dataclass
+class Mesh:
+    """A triangle list: ``tri[t] = (a, b, c)`` counter-clockwise, ids < ``nverts``."""
+
+    tri: np.ndarray  # uint32[T, 3], C-contiguous
+    nverts: int
+    kind: str = ""
+    max_vertices: int = 64
+    max_triangles: int = 126
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ntri(self) -> int:
+        return int(self.tri.shape[0])
+
+
+def _finish(tri: np.ndarray, nverts: int, rng: np.random.Generator | None,
+            permute: bool) -> np.ndarray:
+    tri = np.asarray(tri, dtype=np.int64)
+    if permute and nverts > 0:
+        perm = rng.permutation(nverts).astype(np.int64)
+        tri = perm[tri]
+    return np.ascontiguousarray(tri, dtype=np.uint32)
+
+
+# --------------------------------------------------------------------------
+# Regular grid
+# --------------------------------------------------------------------------
+
+def grid(nx: int, ny: int, rng: np.random.Generator, permute: bool = True) -> Mesh:
+    """``nx`` x ``ny`` quads on an ``(nx+1)`` x ``(ny+1)`` lattice.
+
+    Each quad is split along a diagonal picked by ``rng.integers(2)``; vertex
+    ids are shuffled by ``rng.permutation`` when ``permute`` is set.  Triangles
+    keep generation order (quad by quad, row-major), two per quad.
+    """
+    if nx <= 0 or ny <= 0:
+        return Mesh(np.zeros((0, 3), np.uint32), 0, "grid")
+    w = nx + 1
+    i = np.tile(np.arange(nx, dtype=np.int64), ny)
+    j = np.repeat(np.arange(ny, dtype=np.int64), nx)
+    a = j * w + i          # (i, j)
+    b = a + 1              # (i+1, j)
+    c = a + w + 1          # (i+1, j+1)
+    d = a + w              # (i, j+1)
+    diag = rng.integers(0, 2, size=nx * ny)
+    t0 = np.where(diag[:, None] == 0, np.stack([a, b, c], 1), np.stack([a, b, d], 1))
+    t1 = np.where(diag[:, None] == 0, np.stack([a, c, d], 1), np.stack([b, c, d], 1))
+    tri = np.stack([t0, t1], 1).reshape(-1, 3)
+    nverts = w * (ny + 1)
+    return Mesh(_finish(tri, nverts, rng, permute), nverts, "grid")
+
+
+# --------------------------------------------------------------------------
+# Icosphere
+# --------------------------------------------------------------------------
+
+def _icosahedron():
+    p = (1.0 + math.sqrt(5.0)) / 2.0
+    v = np.array([[-1, p, 0], [1, p, 0], [-1, -p, 0], [1, -p, 0],
+                  [0, -1, p], [0, 1, p], [0, -1, -p], [0, 1, -p],
+                  [p, 0, -1], [p, 0, 1], [-p, 0, -1], [-p, 0, 1]], dtype=np.float64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    f = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+                  [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+                  [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+                  [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], dtype=np.int64)
+    return v, f
+
+
+@lru_cache(maxsize=12)
+def icosphere(level: int):
+    """Unit icosphere after ``level`` 1-to-4 subdivisions (outward CCW).
+
+    Returns ``(positions float64[V,3], faces int64[20*4**level, 3])`` with
+    ``V = 10*4**level + 2``.  Cached per level; callers must not modify.
+    """
+    v, f = _icosahedron()
+    for _ in range(level):
+        nv = v.shape[0]
+        e = np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]], 0)
+        lo = np.minimum(e[:, 0], e[:, 1])
+        hi = np.maximum(e[:, 0], e[:, 1])
+        key = lo * nv + hi
+        uniq, inv = np.unique(key, return_inverse=True)
+        mid = (v[uniq // nv] + v[uniq % nv]) * 0.5
+        mid /= np.linalg.norm(mid, axis=1, keepdims=True)
+        nf = f.shape[0]
+        m = nv + inv
+        ab, bc, ca = m[:nf], m[nf:2 * nf], m[2 * nf:]
+        a, b, c = f[:, 0], f[:, 1], f[:, 2]
+        f = np.stack([np.stack([a, ab, ca], 1), np.stack([ab, b, bc], 1),
+                      np.stack([ca, bc, c], 1), np.stack([ab, bc, ca], 1)], 1).reshape(-1, 3)
+        v = np.concatenate([v, mid], 0)
+    v.setflags(write=False)
+    f.setflags(write=False)
+    return v, f
+
+
+def sphere(level: int, rng: np.random.Generator, permute: bool = True,
+           jitter: float = 0.1) -> Mesh:
+    """Whole icosphere, vertex ids shuffled.  Positions get per-coordinate
+    Gaussian jitter of ``jitter`` x the mean edge length; connectivity does not
+    depend on them and the codec never reads them."""
+    v, f = icosphere(level)
+    nverts = v.shape[0]
+    edge = np.linalg.norm(v[f[:, 0]] - v[f[:, 1]], axis=1).mean()
+    pos = v + rng.normal(0.0, jitter * edge, size=v.shape)
+    tri = np.asarray(f)
+    if permute:
+        perm = rng.permutation(nverts).astype(np.int64)
+        tri = perm[tri]
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(nverts)
+        pos = pos[inv]
+    return Mesh(np.ascontiguousarray(tri, np.uint32), nverts, "sphere",
+                meta={"positions": pos, "level": level})
+
+
+def sphere_patch(n: int, rng: np.random.Generator, permute: bool = True) -> Mesh:
+    """About ``n`` connected triangles cut from the smallest icosphere with at
+    least ``n`` faces: the ``n`` faces whose centroids lie closest to a seeded
+    direction (a spherical cap), vertex ids compacted then shuffled."""
+    n = max(1, int(n))
+    level = 0
+    while 20 * 4 ** level < n:
+        level += 1
+    v, f = icosphere(level)
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    cen = v[f[:, 0]] + v[f[:, 1]] + v[f[:, 2]]
+    score = cen[:, 0] * d[0] + cen[:, 1] * d[1] + cen[:, 2] * d[2]
+    if n < f.shape[0]:
+        sel = np.argpartition(-score, n - 1)[:n]
+        sel.sort()
+    else:
+        sel = np.arange(f.shape[0])
+    sub = np.asarray(f)[sel]
+    used = np.zeros(v.shape[0], np.int64)
+    used[sub.ravel()] = 1
+    remap = np.cumsum(used) - 1
+    tri = remap[sub]
+    nverts = int(used.sum())
+    return Mesh(_finish(tri, nverts, rng, permute), nverts, "patch", meta={"level": level})
+
+
+# --------------------------------------------------------------------------
+# Delaunay
+# --------------------------------------------------------------------------
+
+def delaunay(n: int, rng: np.random.Generator) -> Mesh:
+    """Delaunay triangulation (Qhull via scipy) of about ``(n+2)/2`` uniform
+    random points in the unit square, every triangle turned counter-clockwise.
+    Yields roughly ``n`` irregular triangles; point order is already random."""
+    from scipy.spatial import Delaunay
+
+    p = max(3, (int(n) + 2) // 2 + int(2.0 * math.sqrt(max(n, 1))))
+    pts = rng.random((p, 2))
+    tri = Delaunay(pts).simplices.astype(np.int64)
+    a, b, c = pts[tri[:, 0]], pts[tri[:, 1]], pts[tri[:, 2]]
+    cross = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0])
+    neg = cross < 0
+    tri[neg] = tri[neg][:, [0, 2, 1]]
+    return Mesh(np.ascontiguousarray(tri, np.uint32), p, "delaunay", meta={"points": pts})
+
+
+# --------------------------------------------------------------------------
+# Workloads
+# --------------------------------------------------------------------------
+
+CAPS = ((32, 64), (64, 126), (128, 256))
+
+
+def loguniform_int(rng: np.random.Generator, lo: float, hi: float) -> int:
+    return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+def grid_for(n: int, rng: np.random.Generator) -> Mesh:
+    w = max(1, math.ceil(math.sqrt(n / 2)))
+    h = max(1, math.ceil(n / (2 * w)))
+    return grid(w, h, rng)
+
+
+def workload1() -> Mesh:
+    """Single 64x64 quad grid: 4225 vertices, 8192 triangles, caps 64v/126t."""
+    m = grid(64, 64, rng_for(1, 0))
+    m.max_vertices, m.max_triangles = 64, 126
+    return m
+
+
+def workload2(level: int = 9) -> Mesh:
+    """Single icosphere at level 9: 5,242,880 triangles, 2,621,442 vertices,
+    caps 64v/126t."""
+    m = sphere(level, rng_for(2, 0))
+    m.max_vertices, m.max_triangles = 64, 126
+    return m
+
+
+def workload3_spec(count: int = 2000, lo: float = 1e3, hi: float = 2e6):
+    """Per-mesh recipe of the batched workload: ``(kind, n, caps)`` for each of
+    ``count`` meshes, drawn from ``rng_for(3, i)`` (so any prefix is stable)."""
+    out = []
+    for i in range(count):
+        r = rng_for(3, i)
+        n = loguniform_int(r, lo, hi)
+        kind = "grid" if r.integers(2) == 0 else "patch"
+        caps = CAPS[int(r.integers(3))]
+        out.append((kind, n, caps))
+    return out
+
+
+def workload3_mesh(i: int, lo: float = 1e3, hi: float = 2e6) -> Mesh:
+    """Mesh ``i`` of the batched workload (jittered grid or sphere patch with
+    triangle count log-uniform in [lo, hi], caps uniform over the three)."""
+    r = rng_for(3, i)
+    n = loguniform_int(r, lo, hi)
+    kind = "grid" if r.integers(2) == 0 else "patch"
+    caps = CAPS[int(r.integers(3))]
+    m = grid_for(n, r) if kind == "grid" else sphere_patch(n, r)
+    m.max_vertices, m.max_triangles = caps
+    m.meta["target_n"] = n
+    return m
+
+
+def workload4_mesh(i: int, lo: float = 5e4, hi: float = 1e6) -> Mesh:
+    """Mesh ``i`` of the stress workload: Delaunay of uniform random points with
+    triangle count log-uniform in [lo, hi], caps 64v/126t."""
+    r = rng_for(4, i)
+    n = loguniform_int(r, lo, hi)
+    m = delaunay(n, r)
+    m.max_vertices, m.max_triangles = 64, 126
+    m.meta["target_n"] = n
+    return m
+
+
+def workload5_mesh(i: int, lo: float = 1e4, hi: float = 2e7) -> Mesh:
+    """Mesh ``i`` of the serving pool: like the batched workload, triangle
+    count log-uniform in [lo, hi]."""
+    r = rng_for(5, i)
+    n = loguniform_int(r, lo, hi)
+    kind = "grid" if r.integers(2) == 0 else "patch"
+    caps = CAPS[int(r.integers(3))]
+    m = grid_for(n, r) if kind == "grid" else sphere_patch(n, r)
+    m.max_vertices, m.max_triangles = caps
+    m.meta["target_n"] = n
+    return m
+
+
+# --------------------------------------------------------------------------
+# Small shapes for tests
+# --------------------------------------------------------------------------
+
+def fan(k: int, rng: np.random.Generator | None = None) -> Mesh:
+    """``k`` triangles around hub vertex 0 (an open fan), CCW."""
+    tri = np.stack([np.zeros(k, np.int64), np.arange(1, k + 1), np.arange(2, k + 2)], 1)
+    return Mesh(np.ascontiguousarray(tri, np.uint32), k + 2, "fan")
+
+
+def disjoint(k: int) -> Mesh:
+    """``k`` triangles that share no vertex."""
+    tri = np.arange(3 * k, dtype=np.int64).reshape(k, 3)
+    return Mesh(np.ascontiguousarray(tri, np.uint32), 3 * k, "disjoint")
