@@ -1,0 +1,233 @@
+/*
+ * gtsr.h -- GTS-Reuse meshlet connectivity codec for MI355X (gfx950).
+ *
+ * Kuth et al., "Towards Practical Meshlet Compression" (VMV 2024):
+ *   - Sec. 3: a mesh is split into meshlets of at most max_vertices vertices
+ *     and max_triangles triangles; each meshlet indexes its own vertices with
+ *     8-bit local indices (3 bytes per triangle, "basic mesh shading").
+ *   - Sec. 4.2: each meshlet's triangles are stored as a generalized triangle
+ *     strip, one L/R flag per triangle; a strip restart costs four degenerate
+ *     triangles; a meshlet whose strip outgrows the triangle limit is split.
+ *   - Sec. 4.3: vertices are renumbered by first appearance in the strip, so
+ *     the strip starts with 0,1,2 and every first appearance is one set
+ *     increment flag; only reused local indices are stored, one byte each.
+ *   - Sec. 1 / Sec. 4: compression happens offline on the CPU, decompression
+ *     on the GPU back to 8-bit local index triples.
+ *
+ * encode_meshlets is the CPU side; decode_meshlets (one mesh) and
+ * decode_meshlets_batched (many meshes, one persistent launch) are the GPU
+ * side.  Every call returns an int status (GTSR_OK or a negative code); no
+ * exception crosses this interface.  gtsr_last_error() describes the last
+ * failure on the calling thread.  All calls are reentrant.
+ *
+ * Stream layout (little-endian; the encoder writes it, the decoders read it)
+ *   meshlets  gtsr_meshlet[meshlet_count], 16 bytes each.
+ *   bits      16 bytes per 64 strip triangles of a meshlet: u64 LR, u64 INC.
+ *             Bit i of chunk c belongs to strip triangle 64c+i.  LR bit 1 = R
+ *             (the strip continues across the right edge of the previous
+ *             triangle), 0 = L (left edge); for triangle 0 the flag gives its
+ *             orientation (L: 0,1,2; R: 1,0,2).  INC bit 1 = the triangle's new
+ *             index is the next new vertex, 0 = the next reuse byte.  Triangle
+ *             0 has no INC bit (stored 0).  Bits at positions >= T_s are 0.
+ *   reuse     one byte per reused local index, meshlet after meshlet.
+ *   Offsets are contiguous: meshlet m+1 starts where meshlet m ends in all
+ *   three arrays and in the output; the first meshlet starts at 0.
+ *   output    uint8[strip_triangles][3]: meshlet m's T_s triples start at
+ *             triangle out_off.  Degenerate (restart) triples are included.
+ */
+#ifndef GTSR_H
+#define GTSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GTSR_OK = 0,
+  GTSR_EINVAL = -1,       /* null pointer, index >= vertex_count, buffer too small, bad config */
+  GTSR_ENOMEM = -2,       /* host allocation failed */
+  GTSR_EDEGENERATE = -3,  /* an input triangle repeats a vertex */
+  GTSR_ELIMIT = -4,       /* caps out of range, or counts overflow 32-bit offsets */
+  GTSR_ECORRUPT = -5,     /* gtsr_validate found a violated stream invariant */
+  GTSR_EHIP = -6          /* a HIP runtime call failed */
+};
+
+/* Per-meshlet descriptor, 16 bytes.  tri_count = T_s (strip triangles,
+ * degenerates included, 1..256); vert_count = V (3..256); the meshlet holds
+ * T_s + 2 - V reuse bytes and ceil(T_s/64) flag chunks. */
+typedef struct gtsr_meshlet {
+  uint32_t chunk_off;   /* first 16-byte flag chunk */
+  uint32_t reuse_off;   /* first reuse byte */
+  uint32_t out_off;     /* first output triangle */
+  uint16_t tri_count;
+  uint16_t vert_count;
+} gtsr_meshlet;
+
+typedef struct gtsr_encode_params {
+  uint32_t max_vertices;    /* 3..256 */
+  uint32_t max_triangles;   /* 1..256; bounds T_s (restart degenerates count) */
+  uint32_t threads;         /* 0 = all hardware threads */
+  uint32_t reserved;        /* must be 0 */
+} gtsr_encode_params;
+
+typedef struct gtsr_encoded gtsr_encoded;   /* opaque, host memory, library-owned */
+
+/* Read-only view into a gtsr_encoded (host pointers, valid until
+ * gtsr_encoded_free).  vertices[vert_off[m] .. vert_off[m+1]) maps meshlet
+ * m's local vertex ids to the input's vertex ids (host-side only; the
+ * decoders never read it).  payload_bits = sum over meshlets of
+ * T_s + (T_s - 1) + 8 * reuse bytes; stored_bytes = sum of
+ * 16 + 16 * chunks + reuse bytes. */
+typedef struct gtsr_encoded_view {
+  uint32_t meshlet_count;
+  uint32_t reserved;
+  uint64_t input_triangles, strip_triangles, restarts, reuse_count, split_meshlets;
+  const gtsr_meshlet* meshlets;
+  const uint8_t* bits;
+  uint64_t bits_bytes;
+  const uint8_t* reuse;
+  uint64_t reuse_bytes;
+  const uint32_t* vertices;
+  const uint64_t* vert_off;     /* meshlet_count + 1 entries */
+  uint64_t payload_bits, stored_bytes;
+} gtsr_encoded_view;
+
+/* One encoded mesh.  For decode_meshlets the three pointers are device
+ * pointers; for gtsr_validate they are host pointers. */
+typedef struct gtsr_stream {
+  const gtsr_meshlet* meshlets;
+  const uint8_t* bits;
+  const uint8_t* reuse;
+  uint32_t meshlet_count;
+  uint32_t reserved;
+  uint64_t bits_bytes;        /* 16 * total chunks */
+  uint64_t reuse_bytes;
+  uint64_t strip_triangles;   /* sum of T_s = output triangles */
+} gtsr_stream;
+
+/* Launch shape for the decoders; NULL selects the built-in defaults. */
+typedef struct gtsr_launch_cfg {
+  uint32_t waves_per_group;     /* 1..16: workgroup of 64*waves threads */
+  uint32_t meshlets_per_wave;   /* decode_meshlets: consecutive meshlets per wave, 1..64 */
+  uint32_t groups_per_cu;       /* decode_meshlets_batched: resident groups per CU, 1..32 */
+  uint32_t reserved;            /* must be 0 */
+} gtsr_launch_cfg;
+
+/* One row of the batched decoder's mesh table (device memory, 64 bytes):
+ * a gtsr_stream's device pointers plus where its output goes. */
+typedef struct gtsr_mesh_entry {
+  const gtsr_meshlet* meshlets;
+  const uint8_t* bits;
+  const uint8_t* reuse;
+  uint8_t* out;               /* device, >= 3 * strip_triangles bytes */
+  uint32_t meshlet_count;
+  uint32_t reserved0;
+  uint64_t bits_bytes;
+  uint64_t reuse_bytes;
+  uint64_t strip_triangles;
+} gtsr_mesh_entry;
+
+/* One work item of the batched decoder: meshlets [first, end) of one mesh. */
+typedef struct gtsr_work_item {
+  uint32_t mesh;
+  uint32_t first;
+  uint32_t end;
+  uint32_t reserved;
+} gtsr_work_item;
+
+/* ---------------------------------------------------------------- CPU side */
+
+/* Split a CCW triangle list into meshlets and encode each (Sec. 3, 4.2, 4.3).
+ * indices: host uint32[triangle_count][3], each < vertex_count, no repeated
+ * vertex in a triangle.  Meshlets are built greedily (the paper uses a
+ * third-party builder and MILP-optimal strips; the greedy rules are stated in
+ * the implementation).  On success *out owns host memory until
+ * gtsr_encoded_free.  An empty mesh gives 0 meshlets.
+ * Errors: EINVAL (null pointer, index >= vertex_count), EDEGENERATE, ELIMIT
+ * (caps out of range, reserved != 0, more than 2^32-1 strip triangles),
+ * ENOMEM. */
+int encode_meshlets(const uint32_t* indices, uint64_t triangle_count, uint32_t vertex_count,
+                    const gtsr_encode_params* params, gtsr_encoded** out);
+
+/* Fill *view with pointers into e.  Errors: EINVAL on null. */
+int gtsr_encoded_view_get(const gtsr_encoded* e, gtsr_encoded_view* view);
+
+void gtsr_encoded_free(gtsr_encoded* e);
+
+/* Full structural check of a host-resident stream: counts in range,
+ * contiguous offsets from 0, array sizes equal to the totals, triangle 0's INC
+ * bit and all bits past T_s clear, increments = V - 3, reuse bytes naming
+ * vertices already introduced.  Returns OK or ECORRUPT (EINVAL on null). */
+int gtsr_validate(const gtsr_stream* host_stream);
+
+/* Build a triangle-balanced work list for decode_meshlets_batched.
+ * host_meshlets[i] points at mesh i's host descriptor array of
+ * meshlet_counts[i] entries.  Items never span two meshes and hold
+ * consecutive meshlets totalling about target_tris strip triangles (at
+ * least one meshlet).  Writes at most capacity items to items (may be NULL
+ * to count) and the number needed to *count.  Errors: EINVAL. */
+int gtsr_plan_batch(const gtsr_meshlet* const* host_meshlets, const uint32_t* meshlet_counts,
+                    uint32_t mesh_count, uint32_t target_tris, gtsr_work_item* items,
+                    uint32_t capacity, uint32_t* count);
+
+/* ---------------------------------------------------------------- GPU side */
+
+/* Decode one mesh on the GPU (Sec. 4.2 / 4.3): one wavefront per run of
+ * consecutive meshlets, one lane per strip triangle.  dev: host struct
+ * holding device pointers.  dev_out: device, out_bytes >= 3 *
+ * strip_triangles.  Enqueued on hip_stream (a hipStream_t; NULL = the null
+ * stream); returns before the work finishes; allocates nothing, never
+ * synchronizes.  Meshlets whose descriptor points outside the given sizes
+ * are skipped (their output bytes are left untouched); gtsr_validate reports
+ * such streams.  Errors: EINVAL (null pointer, out_bytes too small, bad
+ * cfg), EHIP (launch failed). */
+int decode_meshlets(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, void* hip_stream);
+
+/* decode_meshlets with an explicit launch shape (cfg may be NULL). */
+int gtsr_decode_meshlets_cfg(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes,
+                             const gtsr_launch_cfg* cfg, void* hip_stream);
+
+/* Decode many meshes in one persistent launch.  dev_mesh_table: device
+ * gtsr_mesh_entry[mesh_count]; dev_work: device gtsr_work_item[work_items]
+ * (gtsr_plan_batch).  Waves pull work items through a counter in
+ * dev_workspace (device, >= gtsr_batched_workspace_bytes(), 256-byte
+ * aligned), which this call clears with a fill kernel before the decode
+ * kernel (no memset node, so the pair may be captured in a graph).  Calls
+ * sharing a workspace must not overlap.  Same skipping rule as
+ * decode_meshlets; work items naming a mesh >= mesh_count are skipped.
+ * Errors: EINVAL, EHIP. */
+int decode_meshlets_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
+                            const gtsr_work_item* dev_work, uint32_t work_items,
+                            void* dev_workspace, uint64_t workspace_bytes,
+                            const gtsr_launch_cfg* cfg, void* hip_stream);
+
+uint64_t gtsr_batched_workspace_bytes(void);
+
+/* Capture decode_meshlets_batched (fill kernel + decode kernel) into an
+ * executable HIP graph once; *graph_exec receives the handle.  The tables and
+ * workspace must stay valid while the graph is used; their contents may
+ * change between launches, their addresses may not.  Errors: EINVAL, EHIP. */
+int gtsr_batched_graph_create(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
+                              const gtsr_work_item* dev_work, uint32_t work_items,
+                              void* dev_workspace, uint64_t workspace_bytes,
+                              const gtsr_launch_cfg* cfg, void** graph_exec);
+
+/* Enqueue a captured graph on hip_stream.  Errors: EINVAL, EHIP. */
+int gtsr_graph_launch(void* graph_exec, void* hip_stream);
+
+void gtsr_graph_destroy(void* graph_exec);
+
+/* Compute units of the current device, as the decoders size persistent
+ * grids.  Returns 0 on error. */
+uint32_t gtsr_device_cu_count(void);
+
+/* Message for the last non-OK return on the calling thread ("" if none). */
+const char* gtsr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GTSR_H */

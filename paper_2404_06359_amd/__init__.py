@@ -1,0 +1,360 @@
+"""MI355X-native GTS-Reuse meshlet connectivity codec.
+
+Thin Python binding over ``libgtsr.so`` (C ABI declared in ``include/gtsr.h``):
+argument marshalling only.  Encoding runs in the library's C++ encoder on the
+host; every decode step runs in the library's HIP kernels.  PyTorch supplies
+device memory and streams.  There is no CPU decode path: if the library is
+missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgtsr.so")
+
+OK, EINVAL, ENOMEM, EDEGENERATE, ELIMIT, ECORRUPT, EHIP = 0, -1, -2, -3, -4, -5, -6
+
+EXPORTED = (
+    "encode_meshlets", "gtsr_encoded_view_get", "gtsr_encoded_free", "gtsr_validate",
+    "gtsr_plan_batch", "decode_meshlets", "gtsr_decode_meshlets_cfg", "decode_meshlets_batched",
+    "gtsr_batched_workspace_bytes", "gtsr_batched_graph_create", "gtsr_graph_launch",
+    "gtsr_graph_destroy", "gtsr_device_cu_count", "gtsr_last_error",
+)
+
+
+class GtsrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Meshlet(C.Structure):
+    _fields_ = [("chunk_off", C.c_uint32), ("reuse_off", C.c_uint32), ("out_off", C.c_uint32),
+                ("tri_count", C.c_uint16), ("vert_count", C.c_uint16)]
+
+
+class EncodeParams(C.Structure):
+    _fields_ = [("max_vertices", C.c_uint32), ("max_triangles", C.c_uint32),
+                ("threads", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class EncodedView(C.Structure):
+    _fields_ = [("meshlet_count", C.c_uint32), ("reserved", C.c_uint32),
+                ("input_triangles", C.c_uint64), ("strip_triangles", C.c_uint64),
+                ("restarts", C.c_uint64), ("reuse_count", C.c_uint64), ("split_meshlets", C.c_uint64),
+                ("meshlets", C.c_void_p), ("bits", C.c_void_p), ("bits_bytes", C.c_uint64),
+                ("reuse", C.c_void_p), ("reuse_bytes", C.c_uint64),
+                ("vertices", C.c_void_p), ("vert_off", C.c_void_p),
+                ("payload_bits", C.c_uint64), ("stored_bytes", C.c_uint64)]
+
+
+class StreamDesc(C.Structure):
+    _fields_ = [("meshlets", C.c_void_p), ("bits", C.c_void_p), ("reuse", C.c_void_p),
+                ("meshlet_count", C.c_uint32), ("reserved", C.c_uint32),
+                ("bits_bytes", C.c_uint64), ("reuse_bytes", C.c_uint64),
+                ("strip_triangles", C.c_uint64)]
+
+
+class LaunchCfg(C.Structure):
+    _fields_ = [("waves_per_group", C.c_uint32), ("meshlets_per_wave", C.c_uint32),
+                ("groups_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+MESH_ENTRY_DTYPE = np.dtype([("meshlets", "<u8"), ("bits", "<u8"), ("reuse", "<u8"), ("out", "<u8"),
+                             ("meshlet_count", "<u4"), ("reserved0", "<u4"), ("bits_bytes", "<u8"),
+                             ("reuse_bytes", "<u8"), ("strip_triangles", "<u8")])
+assert MESH_ENTRY_DTYPE.itemsize == 64
+WORK_ITEM_DTYPE = np.dtype([("mesh", "<u4"), ("first", "<u4"), ("end", "<u4"), ("reserved", "<u4")])
+MESHLET_DTYPE = np.dtype([("chunk_off", "<u4"), ("reuse_off", "<u4"), ("out_off", "<u4"),
+                          ("tri_count", "<u2"), ("vert_count", "<u2")])
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libgtsr.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2404_06359_amd.build.build() "
+                           "(there is no fallback decode path)")
+    L = C.CDLL(LIB_PATH)
+    vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
+    sig = {
+        "encode_meshlets": (C.c_int, [vp, u64, u32, C.POINTER(EncodeParams), C.POINTER(vp)]),
+        "gtsr_encoded_view_get": (C.c_int, [vp, C.POINTER(EncodedView)]),
+        "gtsr_encoded_free": (None, [vp]),
+        "gtsr_validate": (C.c_int, [C.POINTER(StreamDesc)]),
+        "gtsr_plan_batch": (C.c_int, [vp, vp, u32, u32, vp, u32, C.POINTER(u32)]),
+        "decode_meshlets": (C.c_int, [C.POINTER(StreamDesc), vp, u64, vp]),
+        "gtsr_decode_meshlets_cfg": (C.c_int, [C.POINTER(StreamDesc), vp, u64, C.POINTER(LaunchCfg), vp]),
+        "decode_meshlets_batched": (C.c_int, [vp, u32, vp, u32, vp, u64, C.POINTER(LaunchCfg), vp]),
+        "gtsr_batched_workspace_bytes": (u64, []),
+        "gtsr_batched_graph_create": (C.c_int, [vp, u32, vp, u32, vp, u64, C.POINTER(LaunchCfg),
+                                                C.POINTER(vp)]),
+        "gtsr_graph_launch": (C.c_int, [vp, vp]),
+        "gtsr_graph_destroy": (None, [vp]),
+        "gtsr_device_cu_count": (u32, []),
+        "gtsr_last_error": (C.c_char_p, []),
+    }
+    for name, (rt, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = rt
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        msg = lib().gtsr_last_error().decode(errors="replace")
+        raise GtsrError(rc, msg)
+
+
+def _cfg(cfg) -> C.POINTER(LaunchCfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, LaunchCfg):
+        return C.byref(cfg)
+    c = LaunchCfg(int(cfg.get("waves_per_group", 0)), int(cfg.get("meshlets_per_wave", 0)),
+                  int(cfg.get("groups_per_cu", 0)), 0)
+    return C.byref(c)
+
+
+# ---------------------------------------------------------------- host side
+
+@dataclass
+class Encoded:
+    """Host-resident encoded mesh (numpy copies of the library's arrays)."""
+
+    meshlets: np.ndarray      # MESHLET_DTYPE[M]
+    bits: np.ndarray          # uint8
+    reuse: np.ndarray         # uint8
+    verts: np.ndarray         # uint32 local -> global
+    vert_off: np.ndarray      # uint64[M+1]
+    stats: dict = field(default_factory=dict)
+
+    @property
+    def meshlet_count(self) -> int:
+        return int(self.meshlets.shape[0])
+
+    @property
+    def strip_triangles(self) -> int:
+        return int(self.stats["strip_triangles"])
+
+    @property
+    def desc_bytes(self) -> np.ndarray:
+        return self.meshlets.view(np.uint8).reshape(-1)
+
+    def host_stream(self) -> StreamDesc:
+        return StreamDesc(self.meshlets.ctypes.data if self.meshlets.size else None,
+                          self.bits.ctypes.data if self.bits.size else None,
+                          self.reuse.ctypes.data if self.reuse.size else None,
+                          self.meshlet_count, 0, self.bits.size, self.reuse.size, self.strip_triangles)
+
+
+def encode(tri: np.ndarray, nverts: int, max_vertices: int = 64, max_triangles: int = 126,
+           threads: int = 0) -> Encoded:
+    """Encode a CCW triangle list (``uint32[T,3]``) with the library encoder."""
+    L = lib()
+    tri = np.ascontiguousarray(tri, dtype=np.uint32).reshape(-1, 3)
+    params = EncodeParams(max_vertices, max_triangles, threads, 0)
+    h = C.c_void_p()
+    _check(L.encode_meshlets(tri.ctypes.data if tri.size else None, tri.shape[0], nverts,
+                             C.byref(params), C.byref(h)))
+    try:
+        v = EncodedView()
+        _check(L.gtsr_encoded_view_get(h, C.byref(v)))
+        M = v.meshlet_count
+
+        def take(ptr, n, dt):
+            if n == 0:
+                return np.zeros(0, dt)
+            buf = (C.c_uint8 * (n * np.dtype(dt).itemsize)).from_address(ptr)
+            return np.frombuffer(buf, dtype=dt, count=n).copy()
+
+        meshlets = take(v.meshlets, M, MESHLET_DTYPE)
+        bits = take(v.bits, v.bits_bytes, np.uint8)
+        reuse = take(v.reuse, v.reuse_bytes, np.uint8)
+        vert_off = take(v.vert_off, M + 1, np.uint64)
+        verts = take(v.vertices, int(vert_off[-1]) if M else 0, np.uint32)
+        stats = {k: int(getattr(v, k)) for k in ("input_triangles", "strip_triangles", "restarts",
+                                                 "reuse_count", "split_meshlets", "payload_bits",
+                                                 "stored_bytes")}
+    finally:
+        L.gtsr_encoded_free(h)
+    return Encoded(meshlets, bits, reuse, verts, vert_off, stats)
+
+
+def validate(enc: Encoded) -> int:
+    """0 if the host stream is structurally valid, else the library's code."""
+    s = enc.host_stream()
+    return lib().gtsr_validate(C.byref(s))
+
+
+def validate_arrays(desc: np.ndarray, bits: np.ndarray, reuse: np.ndarray, strip_triangles: int) -> int:
+    desc = np.ascontiguousarray(desc, np.uint8)
+    bits = np.ascontiguousarray(bits, np.uint8)
+    reuse = np.ascontiguousarray(reuse, np.uint8)
+    s = StreamDesc(desc.ctypes.data if desc.size else None, bits.ctypes.data if bits.size else None,
+                   reuse.ctypes.data if reuse.size else None, desc.size // 16, 0, bits.size, reuse.size,
+                   strip_triangles)
+    return lib().gtsr_validate(C.byref(s))
+
+
+def plan_batch(meshlet_arrays, target_tris: int = 2048) -> np.ndarray:
+    """Triangle-balanced work list (``WORK_ITEM_DTYPE``) over several meshes'
+    host descriptor arrays."""
+    L = lib()
+    n = len(meshlet_arrays)
+    arrs = [np.ascontiguousarray(a, MESHLET_DTYPE) for a in meshlet_arrays]
+    ptrs = (C.c_void_p * max(n, 1))(*[a.ctypes.data if a.size else None for a in arrs])
+    counts = np.array([a.shape[0] for a in arrs] or [0], np.uint32)
+    cnt = C.c_uint32()
+    _check(L.gtsr_plan_batch(ptrs, counts.ctypes.data, n, target_tris, None, 0, C.byref(cnt)))
+    items = np.zeros(cnt.value, WORK_ITEM_DTYPE)
+    _check(L.gtsr_plan_batch(ptrs, counts.ctypes.data, n, target_tris,
+                             items.ctypes.data if items.size else None, cnt.value, C.byref(cnt)))
+    return items
+
+
+# -------------------------------------------------------------- device side
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class DeviceStream:
+    """One encoded mesh resident in device memory (torch uint8 tensors)."""
+
+    meshlets: object
+    bits: object
+    reuse: object
+    meshlet_count: int
+    strip_triangles: int
+    input_triangles: int = 0
+
+    def desc(self) -> StreamDesc:
+        return StreamDesc(self.meshlets.data_ptr(), self.bits.data_ptr(), self.reuse.data_ptr(),
+                          self.meshlet_count, 0, self.bits.numel(), self.reuse.numel(),
+                          self.strip_triangles)
+
+    @property
+    def nbytes(self) -> int:
+        return self.meshlets.numel() + self.bits.numel() + self.reuse.numel()
+
+
+def to_device(enc: Encoded, device="cuda") -> DeviceStream:
+    torch = _torch()
+
+    def up(a):
+        t = torch.from_numpy(np.ascontiguousarray(a).view(np.uint8).reshape(-1))
+        if t.numel() == 0:
+            return torch.zeros(16, dtype=torch.uint8, device=device)[:0]
+        return t.to(device)
+
+    return DeviceStream(up(enc.meshlets), up(enc.bits), up(enc.reuse), enc.meshlet_count,
+                        enc.strip_triangles, int(enc.stats.get("input_triangles", 0)))
+
+
+def decode(ds: DeviceStream, out=None, stream=None, cfg=None):
+    """Decode one mesh on the GPU; returns ``uint8[strip_triangles, 3]``."""
+    torch = _torch()
+    L = lib()
+    if out is None:
+        out = torch.empty((ds.strip_triangles, 3), dtype=torch.uint8, device=ds.meshlets.device)
+    d = ds.desc()
+    _check(L.gtsr_decode_meshlets_cfg(C.byref(d), out.data_ptr(), out.numel(), _cfg(cfg),
+                                      _stream_handle(stream)))
+    return out
+
+
+class Batch:
+    """Many device-resident meshes decoded by one persistent launch.
+
+    Holds the device mesh table, the work list, the workspace and one output
+    tensor per mesh (views into a single allocation)."""
+
+    def __init__(self, streams, target_tris: int = 2048, host_meshlets=None, device="cuda", outs=None):
+        torch = _torch()
+        self.streams = list(streams)
+        n = len(self.streams)
+        tris = [s.strip_triangles for s in self.streams]
+        if outs is None:
+            total = sum(tris)
+            self.out_all = torch.empty(3 * total + 16, dtype=torch.uint8, device=device)
+            outs, off = [], 0
+            for t in tris:
+                outs.append(self.out_all[3 * off: 3 * (off + t)].view(t, 3))
+                off += t
+        self.outs = outs
+        table = np.zeros(n, MESH_ENTRY_DTYPE)
+        for i, (s, o) in enumerate(zip(self.streams, self.outs)):
+            table[i] = (s.meshlets.data_ptr(), s.bits.data_ptr(), s.reuse.data_ptr(), o.data_ptr(),
+                        s.meshlet_count, 0, s.bits.numel(), s.reuse.numel(), s.strip_triangles)
+        self.table = torch.from_numpy(table.view(np.uint8).reshape(-1)).to(device)
+        if host_meshlets is None:
+            host_meshlets = [s.meshlets.cpu().numpy().view(MESHLET_DTYPE) for s in self.streams]
+        items = plan_batch(host_meshlets, target_tris)
+        self.work_items = int(items.shape[0])
+        self.work = torch.from_numpy(items.view(np.uint8).reshape(-1).copy()).to(device)
+        ws = int(lib().gtsr_batched_workspace_bytes())
+        self.workspace = torch.zeros(ws, dtype=torch.uint8, device=device)
+        self.mesh_count = n
+        self._graphs = []
+
+    def launch(self, stream=None, cfg=None):
+        L = lib()
+        _check(L.decode_meshlets_batched(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
+                                         self.work_items, self.workspace.data_ptr(),
+                                         self.workspace.numel(), _cfg(cfg), _stream_handle(stream)))
+        return self.outs
+
+    def graph(self, cfg=None):
+        """Capture the batched decode once; returns a callable launching it."""
+        L = lib()
+        h = C.c_void_p()
+        _check(L.gtsr_batched_graph_create(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
+                                           self.work_items, self.workspace.data_ptr(),
+                                           self.workspace.numel(), _cfg(cfg), C.byref(h)))
+        g = Graph(h)
+        self._graphs.append(g)
+        return g
+
+
+class Graph:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __call__(self, stream=None):
+        _check(lib().gtsr_graph_launch(self.handle, _stream_handle(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().gtsr_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_cu_count() -> int:
+    return int(lib().gtsr_device_cu_count())

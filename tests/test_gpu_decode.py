@@ -1,0 +1,194 @@
+"""GPU parity: the HIP decoders against the oracle's strip walk, byte for byte.
+
+Inputs are hand-packed streams (every stream up to T_s = 6, random long
+streams) and meshes encoded by the oracle encoder.  Expected outputs always
+come from the oracle decoder on the same bytes.
+"""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle as O
+from streams import all_streams, pack, random_stream
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2404_06359_amd as P  # noqa: E402
+
+CFGS = [None,
+        {"waves_per_group": 1, "meshlets_per_wave": 1},
+        {"waves_per_group": 16, "meshlets_per_wave": 1},
+        {"waves_per_group": 4, "meshlets_per_wave": 64},
+        {"waves_per_group": 2, "meshlets_per_wave": 7}]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def device_stream(desc, bits, reuse, ts):
+    dev = "cuda"
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.uint8)).to(dev) if a.size else \
+        torch.zeros(16, dtype=torch.uint8, device=dev)[:0]
+    return P.DeviceStream(up(desc), up(bits), up(reuse), desc.size // 16, ts)
+
+
+def gpu_decode(desc, bits, reuse, ts, cfg=None, fill=0xAA):
+    ds = device_stream(desc, bits, reuse, ts)
+    out = torch.full((ts, 3), fill, dtype=torch.uint8, device="cuda")
+    P.decode(ds, out=out, cfg=cfg)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def assert_parity(desc, bits, reuse, ts, cfgs=(None,), tag=""):
+    ref = O.decode_arrays(desc, bits, reuse, ts)
+    for cfg in cfgs:
+        for fill in (0xAA, 0x55):
+            say(f"[gpu] {tag} cfg={cfg} fill={fill:#x} meshlets={desc.size // 16} tris={ts}")
+            got = gpu_decode(desc, bits, reuse, ts, cfg, fill)
+            if not np.array_equal(got, ref):
+                bad = np.nonzero((got != ref).any(axis=1))[0]
+                pytest.fail(f"{tag} cfg={cfg}: {bad.size} triangles differ, first {bad[:5]}: "
+                            f"got {got[bad[:5]].tolist()} want {ref[bad[:5]].tolist()}")
+
+
+def test_exhaustive_small_streams():
+    ms = [m for T in range(1, 7) for m in all_streams(T)]
+    desc, bits, reuse, ts = pack(ms)
+    assert_parity(desc, bits, reuse, ts, CFGS, "exhaustive T_s<=6")
+
+
+def test_random_long_streams():
+    rng = np.random.default_rng(2024)
+    ms = []
+    for _ in range(3000):
+        T = int(rng.integers(1, 257))
+        ms.append(random_stream(rng, T, p_inc=float(rng.uniform(0.05, 0.95)),
+                                p_r=float(rng.uniform(0.02, 0.98))))
+    for T in (63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256):
+        ms.append(([0] * T, [0] + [1] * min(T - 1, 253) + [0] * max(0, T - 1 - 253), [0] * max(0, T - 1 - 253)))
+        ms.append(([1] * T, [0] + [1] * min(T - 1, 253) + [0] * max(0, T - 1 - 253), [1] * max(0, T - 1 - 253)))
+    desc, bits, reuse, ts = pack(ms)
+    assert_parity(desc, bits, reuse, ts, CFGS, "random long")
+
+
+MESHES = {
+    "grid64x64": lambda: meshgen.workload1(),
+    "sphere5": lambda: meshgen.sphere(5, meshgen.rng_for(2, 1)),
+    "patch": lambda: meshgen.sphere_patch(30000, meshgen.rng_for(3, 2)),
+    "delaunay": lambda: meshgen.delaunay(40000, meshgen.rng_for(4, 2)),
+}
+
+
+@pytest.mark.parametrize("caps", [(32, 64), (64, 126), (128, 256), (256, 256), (8, 7)])
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_encoded_meshes(name, caps):
+    m = MESHES[name]()
+    s = O.encode(m.tri, m.nverts, *caps)
+    assert_parity(s.desc, s.bits, s.reuse, s.strip_triangles, CFGS[:3], f"{name} {caps}")
+
+
+def test_library_stream_equals_oracle_stream_and_decodes():
+    m = meshgen.workload1()
+    so = O.encode(m.tri, m.nverts, 64, 126)
+    sl = P.encode(m.tri, m.nverts, 64, 126)
+    assert np.array_equal(so.desc, sl.desc_bytes) and np.array_equal(so.bits, sl.bits)
+    assert np.array_equal(so.reuse, sl.reuse)
+    ds = P.to_device(sl)
+    got = P.decode(ds).cpu().numpy()
+    np.testing.assert_array_equal(got, O.decode(so))
+    np.testing.assert_array_equal(O.round_trip_triangles(so, got), O.canonical(m.tri))
+
+
+def test_empty_stream():
+    ds = device_stream(np.zeros(0, np.uint8), np.zeros(0, np.uint8), np.zeros(0, np.uint8), 0)
+    out = P.decode(ds)
+    torch.cuda.synchronize()
+    assert out.shape == (0, 3)
+
+
+def test_out_too_small_is_rejected():
+    desc, bits, reuse, ts = pack([([0, 1, 0], [0, 1, 1], [])])
+    ds = device_stream(desc, bits, reuse, ts)
+    out = torch.zeros((ts - 1, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.GtsrError) as e:
+        P.decode(ds, out=out)
+    assert e.value.code == P.EINVAL
+
+
+def _batched_meshes():
+    meshes = []
+    for i in range(12):
+        r = meshgen.rng_for(3, 100 + i)
+        n = meshgen.loguniform_int(r, 200, 60000)
+        mesh = meshgen.grid_for(n, r) if i % 2 == 0 else meshgen.sphere_patch(n, r)
+        caps = meshgen.CAPS[i % 3]
+        meshes.append((mesh, caps))
+    meshes.append((meshgen.fan(1), (3, 1)))
+    return meshes
+
+
+@pytest.mark.parametrize("target", [1, 300, 2048, 100000])
+def test_batched_persistent(target):
+    encs, refs = [], []
+    for mesh, caps in _batched_meshes():
+        s = O.encode(mesh.tri, mesh.nverts, *caps)
+        encs.append(s)
+        refs.append(O.decode(s))
+    streams = [device_stream(s.desc, s.bits, s.reuse, s.strip_triangles) for s in encs]
+    host = [s.desc.view(P.MESHLET_DTYPE) for s in encs]
+    for cfg in (None, {"waves_per_group": 1, "groups_per_cu": 1}, {"waves_per_group": 16, "groups_per_cu": 2}):
+        say(f"[gpu] batched target={target} cfg={cfg}")
+        b = P.Batch(streams, target_tris=target, host_meshlets=host)
+        b.out_all.fill_(0xAA)
+        b.launch(cfg=cfg)
+        torch.cuda.synchronize()
+        for o, ref in zip(b.outs, refs):
+            np.testing.assert_array_equal(o.cpu().numpy(), ref)
+
+
+def test_batched_graph_replays():
+    encs = [O.encode(m.tri, m.nverts, *caps) for m, caps in _batched_meshes()]
+    refs = [O.decode(s) for s in encs]
+    streams = [device_stream(s.desc, s.bits, s.reuse, s.strip_triangles) for s in encs]
+    b = P.Batch(streams, target_tris=1024, host_meshlets=[s.desc.view(P.MESHLET_DTYPE) for s in encs])
+    g = b.graph()
+    for rep in range(5):
+        say(f"[gpu] graph replay {rep}")
+        b.out_all.fill_(0x55 if rep % 2 else 0xAA)
+        torch.cuda.synchronize()
+        g()
+        torch.cuda.synchronize()
+        for o, ref in zip(b.outs, refs):
+            np.testing.assert_array_equal(o.cpu().numpy(), ref)
+        # unrelated eager work between replays
+        x = torch.randn(1024, device="cuda").sum()
+        del x
+    g.close()
+
+
+def test_full_size_single_mesh():
+    """The 5.2M-triangle icosphere (64v/126t caps) in the plain launch shape
+    the benchmark uses: library stream == oracle stream, GPU decode == oracle
+    decode for every triangle, and the round trip restores the mesh."""
+    m = meshgen.workload2()
+    say(f"[gpu] full-size sphere: {m.ntri} triangles")
+    sl = P.encode(m.tri, m.nverts, 64, 126)
+    so = O.encode(m.tri, m.nverts, 64, 126)
+    assert np.array_equal(so.desc, sl.desc_bytes) and np.array_equal(so.bits, sl.bits)
+    assert np.array_equal(so.reuse, sl.reuse) and np.array_equal(so.verts, sl.verts)
+    ds = P.to_device(sl)
+    out = torch.full((ds.strip_triangles, 3), 0xAA, dtype=torch.uint8, device="cuda")
+    P.decode(ds, out=out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    np.testing.assert_array_equal(got, O.decode(so))

@@ -1,0 +1,155 @@
+"""CPU checks of the product library: exports, encoder, validator, planner.
+
+No GPU compute here.  The library encoder must write byte-for-byte the same
+streams as the oracle encoder (both follow the same greedy rules); the
+library's stream validator must accept and reject exactly what the oracle's
+checker does.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle as O
+import paper_2404_06359_amd as P
+from paper_2404_06359_amd import build as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _libs():
+    if not os.path.exists(P.LIB_PATH):
+        B.build()
+    O.lib()
+    P.lib()
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "gtsr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", src)
+    keywords = {"if", "sizeof", "defined"}
+    return sorted({n for n in names if n not in keywords})
+
+
+def test_library_exports_every_header_function():
+    import ctypes
+    lib = ctypes.CDLL(P.LIB_PATH)
+    names = header_functions()
+    assert "encode_meshlets" in names and "decode_meshlets" in names
+    assert "decode_meshlets_batched" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(P.EXPORTED)
+
+
+def test_struct_layouts_match_header():
+    import ctypes
+    assert ctypes.sizeof(P.Meshlet) == 16
+    assert ctypes.sizeof(P.EncodeParams) == 16
+    assert ctypes.sizeof(P.LaunchCfg) == 16
+    assert P.MESH_ENTRY_DTYPE.itemsize == 64
+    assert P.WORK_ITEM_DTYPE.itemsize == 16
+    assert P.MESHLET_DTYPE.itemsize == 16
+
+
+def _same(so, sl):
+    return (np.array_equal(so.desc, sl.desc_bytes) and np.array_equal(so.bits, sl.bits)
+            and np.array_equal(so.reuse, sl.reuse) and np.array_equal(so.verts, sl.verts)
+            and np.array_equal(so.vert_off, sl.vert_off) and so.stats == sl.stats)
+
+
+MESHES = {
+    "grid64": lambda: meshgen.workload1(),
+    "sphere5": lambda: meshgen.sphere(5, meshgen.rng_for(2, 7)),
+    "patch": lambda: meshgen.sphere_patch(20000, meshgen.rng_for(3, 9)),
+    "delaunay": lambda: meshgen.delaunay(20000, meshgen.rng_for(4, 9)),
+    "fan": lambda: meshgen.fan(255),
+    "disjoint": lambda: meshgen.disjoint(40),
+}
+
+
+@pytest.mark.parametrize("caps", [(32, 64), (64, 126), (128, 256), (256, 256), (3, 1), (8, 7), (5, 9)])
+@pytest.mark.parametrize("name", sorted(MESHES))
+@pytest.mark.parametrize("threads", [1, 3])
+def test_library_encoder_matches_oracle(name, caps, threads):
+    m = MESHES[name]()
+    so = O.encode(m.tri, m.nverts, *caps)
+    sl = P.encode(m.tri, m.nverts, *caps, threads=threads)
+    assert _same(so, sl)
+    assert P.validate(sl) == 0
+
+
+def test_library_encoder_matches_oracle_shuffled_subsets():
+    rng = np.random.default_rng(5)
+    base = meshgen.grid(6, 5, rng, permute=False)
+    for _ in range(200):
+        k = int(rng.integers(1, base.ntri + 1))
+        sub = base.tri[np.sort(rng.choice(base.ntri, k, replace=False))].astype(np.int64)
+        sub = rng.permutation(base.nverts)[sub]
+        sub = sub[rng.permutation(k)]
+        rot = rng.integers(0, 3, k)
+        sub = np.array([np.roll(x, -r) for x, r in zip(sub, rot)], np.uint32)
+        caps = [(3, 1), (4, 3), (6, 10), (64, 126)][int(rng.integers(4))]
+        assert _same(O.encode(sub, base.nverts, *caps), P.encode(sub, base.nverts, *caps, threads=2))
+
+
+def test_encoder_errors():
+    with pytest.raises(P.GtsrError) as e:
+        P.encode(np.array([[0, 1, 1]], np.uint32), 3)
+    assert e.value.code == P.EDEGENERATE and "repeated" in str(e.value)
+    with pytest.raises(P.GtsrError) as e:
+        P.encode(np.array([[0, 1, 3]], np.uint32), 3)
+    assert e.value.code == P.EINVAL
+    for caps in ((2, 126), (257, 126), (64, 0), (64, 257)):
+        with pytest.raises(P.GtsrError) as e:
+            P.encode(np.array([[0, 1, 2]], np.uint32), 3, *caps)
+        assert e.value.code == P.ELIMIT
+    e = P.encode(np.zeros((0, 3), np.uint32), 0)
+    assert e.meshlet_count == 0 and e.strip_triangles == 0 and e.vert_off.tolist() == [0]
+
+
+def test_validator_agrees_with_oracle_on_corruptions():
+    m = meshgen.workload1()
+    s = O.encode(m.tri, m.nverts, 64, 126)
+    rng = np.random.default_rng(3)
+    assert P.validate_arrays(s.desc, s.bits, s.reuse, s.strip_triangles) == 0
+    trials = 0
+    for _ in range(600):
+        desc, bits, reuse, ts = s.desc.copy(), s.bits.copy(), s.reuse.copy(), s.strip_triangles
+        which = int(rng.integers(5))
+        if which == 0:
+            i = int(rng.integers(desc.size)); desc[i] ^= np.uint8(1 << int(rng.integers(8)))
+        elif which == 1:
+            i = int(rng.integers(bits.size)); bits[i] ^= np.uint8(1 << int(rng.integers(8)))
+        elif which == 2:
+            i = int(rng.integers(reuse.size)); reuse[i] = np.uint8(rng.integers(256))
+        elif which == 3:
+            reuse = reuse[:-int(rng.integers(1, 4))]
+        else:
+            ts += int(rng.integers(-2, 3))
+        a = O.check_stream(desc, bits, reuse, ts)
+        b = P.validate_arrays(desc, bits, reuse, ts)
+        assert (a == 0) == (b == 0), (which, a, b)
+        trials += a != 0
+    assert trials > 300
+
+
+def test_plan_batch():
+    encs = [P.encode(m.tri, m.nverts, 64, 126) for m in (meshgen.workload1(), meshgen.fan(5),
+                                                         meshgen.sphere(3, meshgen.rng_for(2, 1)))]
+    for target in (1, 100, 2048, 10 ** 9):
+        items = P.plan_batch([e.meshlets for e in encs], target)
+        # items cover every meshlet of every mesh exactly once, in order
+        for i, e in enumerate(encs):
+            mine = items[items["mesh"] == i]
+            assert mine["first"][0] == 0 and mine["end"][-1] == e.meshlet_count
+            assert np.all(mine["first"][1:] == mine["end"][:-1])
+            assert np.all(mine["end"] > mine["first"])
+            tris = [int(e.meshlets["tri_count"][a:b].sum()) for a, b in zip(mine["first"], mine["end"])]
+            for (a, b), t in zip(zip(mine["first"], mine["end"]), tris):
+                assert t <= target or b - a == 1
+    assert P.plan_batch([], 10).size == 0
