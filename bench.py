@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Throughput of GTS-Reuse meshlet connectivity decode on one MI355X.
+
+Default workload (one step = one decode of all of it): 2000 synthetic meshes
+(regular grids and sphere patches, triangle counts log-uniform in [1e3, 2e6],
+meshlet caps drawn from 32v/64t, 64v/126t, 128v/256t), encoded on the host,
+resident in HBM, decoded by one persistent HIP-graph launch.  Beside it: the
+same meshes decoded with one plain launch per mesh, and the oracle's
+sequential decoder timed on the host cores.
+
+Prints one JSON line (rank 0).  ``--gpus`` above 1 is refused: the decode has
+no cross-GPU step and this benchmark drives a single device.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2404_06359_amd", "csrc", "decode.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source for this workload."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_batched(count: int, threads: int):
+    import meshgen
+    import paper_2404_06359_amd as P
+
+    def one(i):
+        m = meshgen.workload3_mesh(i)
+        e = P.encode(m.tri, m.nverts, m.max_vertices, m.max_triangles, threads=1)
+        return i, e
+
+    encs = [None] * count
+    with ThreadPoolExecutor(threads) as ex:
+        for i, e in ex.map(one, range(count)):
+            encs[i] = e
+    return encs
+
+
+def build_sphere():
+    import meshgen
+    import paper_2404_06359_amd as P
+
+    m = meshgen.workload2()
+    return [P.encode(m.tri, m.nverts, 64, 126, threads=0)]
+
+
+def algorithmic_bytes(encs) -> int:
+    """Per launch: every descriptor (16 B), flag chunk (16 B per 64 strip
+    triangles) and reuse byte read once; 3 output bytes per strip triangle
+    written once."""
+    total = 0
+    for e in encs:
+        total += e.meshlets.nbytes + e.bits.nbytes + e.reuse.nbytes + 3 * e.strip_triangles
+    return total
+
+
+def cpu_baseline(encs, pool, threads):
+    """The oracle's sequential strip walk over every mesh of the workload on
+    `threads` host threads (one task per mesh); its output is compared with
+    the GPU's."""
+    import oracle
+
+    oracle.lib()
+    outs = [np.empty((e.strip_triangles, 3), np.uint8) for e in encs]
+
+    def one(i):
+        e = encs[i]
+        oracle.decode_arrays(e.desc_bytes, e.bits, e.reuse, e.strip_triangles, out=outs[i])
+
+    order = sorted(range(len(encs)), key=lambda i: -encs[i].strip_triangles)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, order))
+        times.append(time.perf_counter() - t0)
+    sec = float(np.median(times))
+    gpu = pool.out.cpu().numpy()
+    same = True
+    for i, o in enumerate(outs):
+        a, b = int(pool.out_offsets[i]), int(pool.out_offsets[i + 1])
+        if not np.array_equal(gpu[a:b], o.reshape(-1)):
+            same = False
+            break
+    tris = int(sum(e.stats["input_triangles"] for e in encs))
+    return {"value": tris / sec / 1e9, "unit": "Gtps", "cores": threads, "kind": "oracle",
+            "sample": f"whole workload ({len(encs)} meshes, {tris} input triangles), sequential strip walk, "
+                      f"one task per mesh, median of 3",
+            "seconds": sec, "matches_gpu_bit_exact": same}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=["batched", "sphere"], default="batched")
+    ap.add_argument("--meshes", type=int, default=2000)
+    ap.add_argument("--target-tris", type=int, default=2048)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--groups-per-cu", type=int, default=0)
+    ap.add_argument("--meshlets-per-wave", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-mesh", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        if int(os.environ.get("RANK", "0")) == 0:
+            print("bench.py measures one GPU only: the meshlet decode has no cross-GPU step, "
+                  "so --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2404_06359_amd as P
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    threads = host_threads()
+
+    t0 = time.perf_counter()
+    encs = build_batched(args.meshes, threads) if args.workload == "batched" else build_sphere()
+    prep_s = time.perf_counter() - t0
+    in_tris = int(sum(e.stats["input_triangles"] for e in encs))
+    strip_tris = int(sum(e.strip_triangles for e in encs))
+    meshlets = int(sum(e.meshlet_count for e in encs))
+    restarts = int(sum(e.stats["restarts"] for e in encs))
+    alg = algorithmic_bytes(encs)
+    log(f"[bench] prep {prep_s:.1f}s: {len(encs)} meshes, {in_tris} triangles, {strip_tris} strip "
+        f"triangles, {meshlets} meshlets, {alg / 1e9:.3f} GB per decode")
+
+    pool = P.Pool(encs, device=dev)
+    cfg = {"waves_per_group": args.waves, "groups_per_cu": args.groups_per_cu,
+           "meshlets_per_wave": args.meshlets_per_wave}
+    stream = torch.cuda.current_stream()
+    if args.workload == "batched":
+        pool.plan(args.target_tris)
+        graph = pool.batched_graph(cfg)
+        step = lambda: graph(stream)
+        kernel = "decode_batched"
+    else:
+        step = lambda: pool.decode_per_mesh(stream, cfg)
+        kernel = "decode_plain"
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"[bench] {kernel}: {ms:.4f} ms per step")
+
+    per_mesh = None
+    if args.workload == "batched" and not args.no_per_mesh:
+        for _ in range(2):
+            pool.decode_per_mesh(stream, cfg)
+        torch.cuda.synchronize()
+        pm_steps = max(3, args.steps // 4)
+        ev0.record(stream)
+        for _ in range(pm_steps):
+            pool.decode_per_mesh(stream, cfg)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        pm_ms = ev0.elapsed_time(ev1) / pm_steps
+        per_mesh = {"value": in_tris / (pm_ms / 1e3) / 1e9, "unit": "Gtps", "ms_per_step": pm_ms,
+                    "launches_per_step": len(encs)}
+        log(f"[bench] per-mesh plain launches: {pm_ms:.4f} ms per step")
+        # leave the batched result in pool.out for the baseline comparison
+        step()
+        torch.cuda.synchronize()
+
+    achieved = alg / (ms / 1e3) / 1e9
+    traffic = read_traffic(kernel, args.workload)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(encs, pool, threads)
+    if cpu:
+        log(f"[bench] cpu baseline: {cpu['value']:.3f} Gtps on {cpu['cores']} threads, "
+            f"bit-exact vs GPU: {cpu['matches_gpu_bit_exact']}")
+
+    if args.workload == "batched":
+        workload = (f"batched: {len(encs)} meshes (grid or sphere patch), 1e3-2e6 triangles each "
+                    "log-uniform, caps mixed 32v/64t 64v/126t 128v/256t, one persistent graph launch")
+    else:
+        workload = "single mesh: icosphere level 9, caps 64v/126t, one plain launch"
+    out = {
+        "metric": "decoded triangles/s (Gtps) + HBM GB/s, batched vs per-mesh",
+        "value": in_tris / (ms / 1e3) / 1e9,
+        "unit": "Gtps",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": workload, "meshes": len(encs), "input_triangles": in_tris,
+                   "strip_triangles": strip_tris, "meshlets": meshlets, "restarts": restarts,
+                   "work_items": pool.work_items, "launch": {k: v for k, v in cfg.items() if v},
+                   "prep_seconds": round(prep_s, 2)},
+        "roofline": roof,
+        "per_mesh": per_mesh,
+        "strip_triangles_per_s": strip_tris / (ms / 1e3),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

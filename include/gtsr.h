@@ -177,9 +177,9 @@ int gtsr_plan_batch(const gtsr_meshlet* const* host_meshlets, const uint32_t* me
 /* Decode one mesh on the GPU (Sec. 4.2 / 4.3): one wavefront per run of
  * consecutive meshlets, one lane per strip triangle.  dev: host struct
  * holding device pointers.  dev_out: device, out_bytes >= 3 *
- * strip_triangles.  Enqueued on hip_stream (a hipStream_t; NULL = the null
- * stream); returns before the work finishes; allocates nothing, never
- * synchronizes.  Meshlets whose descriptor points outside the given sizes
+ * strip_triangles.  dev->meshlets and dev->bits must be 16-byte aligned.
+ * Enqueued on hip_stream (a hipStream_t; NULL = the null stream); returns
+ * before the work finishes; allocates nothing, never synchronizes.  Meshlets whose descriptor points outside the given sizes
  * are skipped (their output bytes are left untouched); gtsr_validate reports
  * such streams.  Errors: EINVAL (null pointer, out_bytes too small, bad
  * cfg), EHIP (launch failed). */
@@ -189,9 +189,19 @@ int decode_meshlets(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes
 int gtsr_decode_meshlets_cfg(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes,
                              const gtsr_launch_cfg* cfg, void* hip_stream);
 
+/* One plain decode launch per mesh, back to back on hip_stream: streams[i]
+ * (host array of structs holding device pointers) into dev_outs[i] (host
+ * array of device pointers) of out_bytes[i] bytes.  Arguments of every mesh
+ * are checked before the first launch; then it behaves as n calls of
+ * gtsr_decode_meshlets_cfg.  Errors: EINVAL, EHIP. */
+int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_outs,
+                              const uint64_t* out_bytes, uint32_t n, const gtsr_launch_cfg* cfg,
+                              void* hip_stream);
+
 /* Decode many meshes in one persistent launch.  dev_mesh_table: device
  * gtsr_mesh_entry[mesh_count]; dev_work: device gtsr_work_item[work_items]
- * (gtsr_plan_batch).  Waves pull work items through a counter in
+ * (gtsr_plan_batch); both 16-byte aligned, as is every entry's meshlets and
+ * bits pointer.  Waves pull work items through a counter in
  * dev_workspace (device, >= gtsr_batched_workspace_bytes(), 256-byte
  * aligned), which this call clears with a fill kernel before the decode
  * kernel (no memset node, so the pair may be captured in a graph).  Calls

@@ -15,13 +15,49 @@ on its own.
 """
 from __future__ import annotations
 
+import ctypes as C
 import math
+import os
+import subprocess
+import threading
 from dataclasses import dataclass, field
-from functools import lru_cache
 
 import numpy as np
 
 SEED_ROOT = (2404, 6359)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmeshgen.so")
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def build() -> str:
+    """Compile ``meshgen.c`` (plain C, gcc) into ``libmeshgen.so``."""
+    tmp = LIB_PATH + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-o", tmp,
+                    os.path.join(HERE, "meshgen.c"), "-lm"], check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _clib():
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                build()
+            L = C.CDLL(LIB_PATH)
+            vp = C.c_void_p
+            L.mg_grid.argtypes = [C.c_uint32, C.c_uint32, vp, vp, vp]
+            L.mg_grid.restype = None
+            L.mg_icosphere.argtypes = [C.c_uint32, vp, vp]
+            L.mg_icosphere.restype = C.c_int
+            L.mg_sphere_patch.argtypes = [vp, C.c_uint64, vp, C.c_uint64, C.c_uint64, vp, vp,
+                                          C.POINTER(C.c_uint32)]
+            L.mg_sphere_patch.restype = C.c_int
+            _lib = L
+    return _lib
 
 
 def rng_for(workload: int, i: int = 0) -> np.random.Generator:
@@ -67,65 +103,41 @@ def grid(nx: int, ny: int, rng: np.random.Generator, permute: bool = True) -> Me
     """
     if nx <= 0 or ny <= 0:
         return Mesh(np.zeros((0, 3), np.uint32), 0, "grid")
-    w = nx + 1
-    i = np.tile(np.arange(nx, dtype=np.int64), ny)
-    j = np.repeat(np.arange(ny, dtype=np.int64), nx)
-    a = j * w + i          # (i, j)
-    b = a + 1              # (i+1, j)
-    c = a + w + 1          # (i+1, j+1)
-    d = a + w              # (i, j+1)
-    diag = rng.integers(0, 2, size=nx * ny)
-    t0 = np.where(diag[:, None] == 0, np.stack([a, b, c], 1), np.stack([a, b, d], 1))
-    t1 = np.where(diag[:, None] == 0, np.stack([a, c, d], 1), np.stack([b, c, d], 1))
-    tri = np.stack([t0, t1], 1).reshape(-1, 3)
-    nverts = w * (ny + 1)
-    return Mesh(_finish(tri, nverts, rng, permute), nverts, "grid")
+    diag = np.ascontiguousarray(rng.integers(0, 2, size=nx * ny).astype(np.uint8))
+    nverts = (nx + 1) * (ny + 1)
+    perm = np.ascontiguousarray(rng.permutation(nverts).astype(np.uint32)) if permute else None
+    tri = np.empty((2 * nx * ny, 3), np.uint32)
+    _clib().mg_grid(nx, ny, diag.ctypes.data, perm.ctypes.data if perm is not None else None,
+                    tri.ctypes.data)
+    return Mesh(tri, nverts, "grid")
 
 
 # --------------------------------------------------------------------------
 # Icosphere
 # --------------------------------------------------------------------------
 
-def _icosahedron():
-    p = (1.0 + math.sqrt(5.0)) / 2.0
-    v = np.array([[-1, p, 0], [1, p, 0], [-1, -p, 0], [1, -p, 0],
-                  [0, -1, p], [0, 1, p], [0, -1, -p], [0, 1, -p],
-                  [p, 0, -1], [p, 0, 1], [-p, 0, -1], [-p, 0, 1]], dtype=np.float64)
-    v /= np.linalg.norm(v, axis=1, keepdims=True)
-    f = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
-                  [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
-                  [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
-                  [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], dtype=np.int64)
-    return v, f
+_ico_cache: dict = {}
+_ico_lock = threading.Lock()
 
 
-@lru_cache(maxsize=12)
 def icosphere(level: int):
     """Unit icosphere after ``level`` 1-to-4 subdivisions (outward CCW).
 
-    Returns ``(positions float64[V,3], faces int64[20*4**level, 3])`` with
+    Returns ``(positions float64[V,3], faces uint32[20*4**level, 3])`` with
     ``V = 10*4**level + 2``.  Cached per level; callers must not modify.
     """
-    v, f = _icosahedron()
-    for _ in range(level):
-        nv = v.shape[0]
-        e = np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]], 0)
-        lo = np.minimum(e[:, 0], e[:, 1])
-        hi = np.maximum(e[:, 0], e[:, 1])
-        key = lo * nv + hi
-        uniq, inv = np.unique(key, return_inverse=True)
-        mid = (v[uniq // nv] + v[uniq % nv]) * 0.5
-        mid /= np.linalg.norm(mid, axis=1, keepdims=True)
-        nf = f.shape[0]
-        m = nv + inv
-        ab, bc, ca = m[:nf], m[nf:2 * nf], m[2 * nf:]
-        a, b, c = f[:, 0], f[:, 1], f[:, 2]
-        f = np.stack([np.stack([a, ab, ca], 1), np.stack([ab, b, bc], 1),
-                      np.stack([ca, bc, c], 1), np.stack([ab, bc, ca], 1)], 1).reshape(-1, 3)
-        v = np.concatenate([v, mid], 0)
-    v.setflags(write=False)
-    f.setflags(write=False)
-    return v, f
+    with _ico_lock:
+        hit = _ico_cache.get(level)
+        if hit is None:
+            nv, nf = 10 * 4 ** level + 2, 20 * 4 ** level
+            v = np.empty((nv, 3), np.float64)
+            f = np.empty((nf, 3), np.uint32)
+            if _clib().mg_icosphere(level, v.ctypes.data, f.ctypes.data) != 0:
+                raise MemoryError("icosphere")
+            v.setflags(write=False)
+            f.setflags(write=False)
+            hit = _ico_cache[level] = (v, f)
+    return hit
 
 
 def sphere(level: int, rng: np.random.Generator, permute: bool = True,
@@ -139,7 +151,7 @@ def sphere(level: int, rng: np.random.Generator, permute: bool = True,
     pos = v + rng.normal(0.0, jitter * edge, size=v.shape)
     tri = np.asarray(f)
     if permute:
-        perm = rng.permutation(nverts).astype(np.int64)
+        perm = rng.permutation(nverts).astype(np.uint32)
         tri = perm[tri]
         inv = np.empty_like(perm)
         inv[perm] = np.arange(nverts)
@@ -158,21 +170,18 @@ def sphere_patch(n: int, rng: np.random.Generator, permute: bool = True) -> Mesh
         level += 1
     v, f = icosphere(level)
     d = rng.normal(size=3)
-    d /= np.linalg.norm(d)
-    cen = v[f[:, 0]] + v[f[:, 1]] + v[f[:, 2]]
-    score = cen[:, 0] * d[0] + cen[:, 1] * d[1] + cen[:, 2] * d[2]
-    if n < f.shape[0]:
-        sel = np.argpartition(-score, n - 1)[:n]
-        sel.sort()
-    else:
-        sel = np.arange(f.shape[0])
-    sub = np.asarray(f)[sel]
-    used = np.zeros(v.shape[0], np.int64)
-    used[sub.ravel()] = 1
-    remap = np.cumsum(used) - 1
-    tri = remap[sub]
-    nverts = int(used.sum())
-    return Mesh(_finish(tri, nverts, rng, permute), nverts, "patch", meta={"level": level})
+    d = np.ascontiguousarray(d / np.linalg.norm(d))
+    tri = np.empty((n, 3), np.uint32)
+    nv = C.c_uint32()
+    rc = _clib().mg_sphere_patch(v.ctypes.data, v.shape[0], f.ctypes.data, f.shape[0], n,
+                                 d.ctypes.data, tri.ctypes.data, C.byref(nv))
+    if rc != 0:
+        raise MemoryError("sphere_patch")
+    nverts = int(nv.value)
+    if permute:
+        perm = rng.permutation(nverts).astype(np.uint32)
+        tri = perm[tri]
+    return Mesh(np.ascontiguousarray(tri, np.uint32), nverts, "patch", meta={"level": level})
 
 
 # --------------------------------------------------------------------------

@@ -21,7 +21,8 @@ OK, EINVAL, ENOMEM, EDEGENERATE, ELIMIT, ECORRUPT, EHIP = 0, -1, -2, -3, -4, -5,
 
 EXPORTED = (
     "encode_meshlets", "gtsr_encoded_view_get", "gtsr_encoded_free", "gtsr_validate",
-    "gtsr_plan_batch", "decode_meshlets", "gtsr_decode_meshlets_cfg", "decode_meshlets_batched",
+    "gtsr_plan_batch", "decode_meshlets", "gtsr_decode_meshlets_cfg", "gtsr_decode_meshlets_many",
+    "decode_meshlets_batched",
     "gtsr_batched_workspace_bytes", "gtsr_batched_graph_create", "gtsr_graph_launch",
     "gtsr_graph_destroy", "gtsr_device_cu_count", "gtsr_last_error",
 )
@@ -94,6 +95,7 @@ def lib():
         "gtsr_plan_batch": (C.c_int, [vp, vp, u32, u32, vp, u32, C.POINTER(u32)]),
         "decode_meshlets": (C.c_int, [C.POINTER(StreamDesc), vp, u64, vp]),
         "gtsr_decode_meshlets_cfg": (C.c_int, [C.POINTER(StreamDesc), vp, u64, C.POINTER(LaunchCfg), vp]),
+        "gtsr_decode_meshlets_many": (C.c_int, [vp, vp, vp, u32, C.POINTER(LaunchCfg), vp]),
         "decode_meshlets_batched": (C.c_int, [vp, u32, vp, u32, vp, u64, C.POINTER(LaunchCfg), vp]),
         "gtsr_batched_workspace_bytes": (u64, []),
         "gtsr_batched_graph_create": (C.c_int, [vp, u32, vp, u32, vp, u64, C.POINTER(LaunchCfg),
@@ -358,3 +360,107 @@ class Graph:
 
 def device_cu_count() -> int:
     return int(lib().gtsr_device_cu_count())
+
+
+class Pool:
+    """Many encoded meshes resident on the device in one allocation per array.
+
+    Each mesh's descriptors, flag chunks and reuse bytes sit at 16-byte
+    aligned offsets of three shared uint8 tensors; ``out`` holds every mesh's
+    decoded triples back to back.  ``table`` is the device mesh table of the
+    batched decoder, ``streams`` the per-mesh ``StreamDesc`` structs (device
+    pointers) of the plain decoder."""
+
+    def __init__(self, encs, device="cuda", out=True):
+        torch = _torch()
+
+        def pad16(n):
+            return (n + 15) // 16 * 16
+
+        n = len(encs)
+        self.mesh_count = n
+        self.meshlet_counts = np.array([e.meshlet_count for e in encs], np.uint32)
+        self.strip_tris = np.array([e.strip_triangles for e in encs], np.uint64)
+        self.input_tris = np.array([e.stats["input_triangles"] for e in encs], np.uint64)
+        d_sz = np.array([e.meshlets.nbytes for e in encs], np.uint64)
+        b_sz = np.array([e.bits.nbytes for e in encs], np.uint64)
+        r_sz = np.array([e.reuse.nbytes for e in encs], np.uint64)
+        d_off = np.concatenate([[0], np.cumsum([pad16(int(x)) for x in d_sz])]).astype(np.uint64)
+        b_off = np.concatenate([[0], np.cumsum([pad16(int(x)) for x in b_sz])]).astype(np.uint64)
+        r_off = np.concatenate([[0], np.cumsum([pad16(int(x)) for x in r_sz])]).astype(np.uint64)
+        o_off = np.concatenate([[0], np.cumsum(3 * self.strip_tris)]).astype(np.uint64)
+        hd = np.zeros(int(d_off[-1]) + 16, np.uint8)
+        hb = np.zeros(int(b_off[-1]) + 16, np.uint8)
+        hr = np.zeros(int(r_off[-1]) + 16, np.uint8)
+        for i, e in enumerate(encs):
+            hd[int(d_off[i]):int(d_off[i]) + int(d_sz[i])] = e.meshlets.view(np.uint8).reshape(-1)
+            hb[int(b_off[i]):int(b_off[i]) + int(b_sz[i])] = e.bits
+            hr[int(r_off[i]):int(r_off[i]) + int(r_sz[i])] = e.reuse
+        self.host_meshlets = [e.meshlets for e in encs]
+        self.d_meshlets = torch.from_numpy(hd).to(device)
+        self.d_bits = torch.from_numpy(hb).to(device)
+        self.d_reuse = torch.from_numpy(hr).to(device)
+        self.out_offsets = o_off
+        self.out = torch.empty(int(o_off[-1]) + 16, dtype=torch.uint8, device=device) if out else None
+        self.stored_bytes = int(d_sz.sum() + b_sz.sum() + r_sz.sum())
+        dm, db, dr = self.d_meshlets.data_ptr(), self.d_bits.data_ptr(), self.d_reuse.data_ptr()
+        do = self.out.data_ptr() if out else 0
+        table = np.zeros(n, MESH_ENTRY_DTYPE)
+        table["meshlets"] = dm + d_off[:-1]
+        table["bits"] = db + b_off[:-1]
+        table["reuse"] = dr + r_off[:-1]
+        table["out"] = do + o_off[:-1]
+        table["meshlet_count"] = self.meshlet_counts
+        table["bits_bytes"] = b_sz
+        table["reuse_bytes"] = r_sz
+        table["strip_triangles"] = self.strip_tris
+        self.host_table = table
+        self.table = torch.from_numpy(table.view(np.uint8).reshape(-1).copy()).to(device)
+        self.streams = (StreamDesc * max(n, 1))()
+        for i in range(n):
+            self.streams[i] = StreamDesc(int(table["meshlets"][i]), int(table["bits"][i]),
+                                         int(table["reuse"][i]), int(self.meshlet_counts[i]), 0,
+                                         int(b_sz[i]), int(r_sz[i]), int(self.strip_tris[i]))
+        self.out_ptrs = (C.c_void_p * max(n, 1))(*[int(x) for x in table["out"]])
+        self.out_bytes = (C.c_uint64 * max(n, 1))(*[int(x) for x in 3 * self.strip_tris])
+        self.work = None
+        self.work_items = 0
+        self.workspace = torch.zeros(int(lib().gtsr_batched_workspace_bytes()), dtype=torch.uint8,
+                                     device=device)
+        self._graphs = []
+
+    def output(self, i: int):
+        """Decoded triples of mesh ``i`` (a view into ``out``)."""
+        a, b = int(self.out_offsets[i]), int(self.out_offsets[i + 1])
+        return self.out[a:b].view(-1, 3)
+
+    def plan(self, target_tris: int = 2048):
+        torch = _torch()
+        items = plan_batch(self.host_meshlets, target_tris)
+        self.work_items = int(items.shape[0])
+        self.work = torch.from_numpy(items.view(np.uint8).reshape(-1).copy()).to(self.table.device) \
+            if items.size else torch.zeros(16, dtype=torch.uint8, device=self.table.device)
+        return self
+
+    def decode_batched(self, stream=None, cfg=None):
+        if self.work is None:
+            self.plan()
+        _check(lib().decode_meshlets_batched(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
+                                             self.work_items, self.workspace.data_ptr(),
+                                             self.workspace.numel(), _cfg(cfg), _stream_handle(stream)))
+
+    def batched_graph(self, cfg=None):
+        if self.work is None:
+            self.plan()
+        h = C.c_void_p()
+        _check(lib().gtsr_batched_graph_create(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
+                                               self.work_items, self.workspace.data_ptr(),
+                                               self.workspace.numel(), _cfg(cfg), C.byref(h)))
+        g = Graph(h)
+        self._graphs.append(g)
+        return g
+
+    def decode_per_mesh(self, stream=None, cfg=None):
+        """One plain launch per mesh, back to back (enqueued from C)."""
+        _check(lib().gtsr_decode_meshlets_many(self.streams, self.out_ptrs, self.out_bytes, self.mesh_count,
+                                               _cfg(cfg), _stream_handle(stream)))

@@ -276,27 +276,58 @@ int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gts
 
 using namespace gtsr;
 
-extern "C" int gtsr_decode_meshlets_cfg(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes,
-                                        const gtsr_launch_cfg* cfg, void* hip_stream) {
-  const char* who = "decode_meshlets";
+namespace gtsr {
+namespace {
+
+int check_plain_args(const gtsr_stream* dev, const uint8_t* dev_out, uint64_t out_bytes) {
   if (!dev) return fail(GTSR_EINVAL, "decode_meshlets: null stream");
-  if (dev->meshlet_count == 0) return ok();
+  if (dev->meshlet_count == 0) return GTSR_OK;
   if (!dev->meshlets || !dev->bits || !dev_out || (dev->reuse_bytes && !dev->reuse))
     return fail(GTSR_EINVAL, "decode_meshlets: null device pointer");
   if (out_bytes / 3 < dev->strip_triangles)
     return fail(GTSR_EINVAL, "decode_meshlets: out_bytes < 3 * strip_triangles");
   if ((reinterpret_cast<uintptr_t>(dev->meshlets) & 15) || (reinterpret_cast<uintptr_t>(dev->bits) & 15))
     return fail(GTSR_EINVAL, "decode_meshlets: meshlets and bits must be 16-byte aligned");
-  Defaults d;
-  if (int rc = resolve_cfg(cfg, d, who)) return rc;
+  const uint64_t groups = (uint64_t(dev->meshlet_count) + 15) / 16 * 16;
+  if (groups > 0x7FFFFFFFull) return fail(GTSR_ELIMIT, "decode_meshlets: grid too large");
+  return GTSR_OK;
+}
+
+void launch_plain(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, const Defaults& d,
+                  hipStream_t stream) {
+  if (dev->meshlet_count == 0) return;
   const uint64_t per_group = uint64_t(d.waves) * d.mpw;
   uint64_t groups = (dev->meshlet_count + per_group - 1) / per_group;
   groups = (groups + kXcds - 1) / kXcds * kXcds;
-  if (groups > 0x7FFFFFFFull) return fail(GTSR_ELIMIT, "decode_meshlets: grid too large");
   hipLaunchKernelGGL(k_decode_plain, dim3(uint32_t(groups)), dim3(kWave * d.waves), d.waves * kIdxBytes,
-                     static_cast<hipStream_t>(hip_stream), dev->meshlets, dev->bits, dev->reuse, dev_out,
-                     dev->meshlet_count, dev->bits_bytes / 16, dev->reuse_bytes, out_bytes / 3, d.mpw);
-  return check_launch(who);
+                     stream, dev->meshlets, dev->bits, dev->reuse, dev_out, dev->meshlet_count,
+                     dev->bits_bytes / 16, dev->reuse_bytes, out_bytes / 3, d.mpw);
+}
+
+}  // namespace
+}  // namespace gtsr
+
+extern "C" int gtsr_decode_meshlets_cfg(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes,
+                                        const gtsr_launch_cfg* cfg, void* hip_stream) {
+  if (int rc = check_plain_args(dev, dev_out, out_bytes)) return rc;
+  Defaults d;
+  if (int rc = resolve_cfg(cfg, d, "decode_meshlets")) return rc;
+  launch_plain(dev, dev_out, out_bytes, d, static_cast<hipStream_t>(hip_stream));
+  return check_launch("decode_meshlets");
+}
+
+extern "C" int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_outs,
+                                         const uint64_t* out_bytes, uint32_t n, const gtsr_launch_cfg* cfg,
+                                         void* hip_stream) {
+  if (n && (!streams || !dev_outs || !out_bytes))
+    return fail(GTSR_EINVAL, "gtsr_decode_meshlets_many: null argument");
+  Defaults d;
+  if (int rc = resolve_cfg(cfg, d, "gtsr_decode_meshlets_many")) return rc;
+  for (uint32_t i = 0; i < n; ++i)
+    if (int rc = check_plain_args(&streams[i], dev_outs[i], out_bytes[i])) return rc;
+  for (uint32_t i = 0; i < n; ++i)
+    launch_plain(&streams[i], dev_outs[i], out_bytes[i], d, static_cast<hipStream_t>(hip_stream));
+  return check_launch("gtsr_decode_meshlets_many");
 }
 
 extern "C" int decode_meshlets(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, void* hip_stream) {
