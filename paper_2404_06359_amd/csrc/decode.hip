@@ -1,27 +1,35 @@
 // GPU decoders for GTS-Reuse meshlet connectivity, written for CDNA4 (gfx950).
 //
-// Kuth et al., "Towards Practical Meshlet Compression", Sec. 4.2 / 4.3: the
-// decoder must produce every triangle independently, without the triangle
-// before it.  Per strip triangle t (one lane each, 64 per chunk):
+// Kuth et al., "Towards Practical Meshlet Compression", Sec. 4.2 / 4.3: every
+// triangle of a strip is produced on its own, without the triangle before it.
+// Per strip triangle t (one lane each, 64 per chunk):
 //
-//   index stream  I[0..2] = 0,1,2;  for t >= 1:  s_t = 2 + sum_{u=1..t} g[u]
-//                 I[t+2] = g[t] ? s_t : reuse[t + 1 - s_t]
-//   pivot         the last flip of the L/R flags at or before t: with the
-//                 change mask  ch[j] = f[j] xor f[j-1]  (ch[0] = 0),
-//                 j_t = max{ j <= t : ch[j] = 1 }  (0 if none) and X_t = I[j_t]
-//                 (equivalently I[k+1] for the last k < t with f[k] != f[t])
-//   triangle      f[t] = L: (X_t, I[t+1], I[t+2]);  R: (I[t+1], X_t, I[t+2])
+//   index stream  I[0..2] = 0,1,2;  for t >= 1 with increment flag g[t] set,
+//                 I[t+2] = s_t = 2 + sum_{u=1..t} g[u]  (prefix count, mbcnt);
+//                 with g[t] clear, I[t+2] = reuse[t + 1 - s_t], where
+//                 t + 1 - s_t is the number of clear flags before t: the rank
+//                 of t among the reuse slots, i.e. mbcnt of the complemented
+//                 increment word plus a carried count.
+//   pivot         the last L/R flip at or before t: with the change word
+//                 ch[j] = f[j] xor f[j-1] (ch[0] = 0), j_t = max{j <= t: ch[j]}
+//                 (0 if none) and X_t = I[j_t] -- the same vertex as I[k+1]
+//                 for the last k < t with f[k] != f[t]; a count-leading-zeros
+//                 of ch shifted so that bit t is the top bit, else the last
+//                 change carried from earlier chunks (fans longer than a word).
+//   triangle      f[t] = L: (X_t, I[t+1], I[t+2]);  R: (I[t+1], X_t, I[t+2]).
 //
-// The flag words are uniform across the wave and sit in scalar registers;
-// s_t is the wave's popcount prefix (mbcnt) of the increment word plus a
-// carried base; j_t is a count-leading-zeros on the change word shifted so
-// that lane t's bit is the top bit, else the last change carried from earlier
-// chunks (fans longer than one word, Sec. 4.2).  I[] lives in LDS, one array
-// per wavefront; each lane writes I[t+2] and reads I[t+1] and I[j_t].
+// Data movement.  A wavefront decodes a run of consecutive meshlets of one
+// mesh: it loads up to 32 descriptors with one vector load, stages the run's
+// flag chunks and reuse bytes in LDS with coalesced loads, decodes each
+// meshlet from LDS into an LDS output tile, then writes the run's output
+// bytes (contiguous in the stream layout) with dword stores.  The chunk loop
+// touches no global memory.  A run holds at most kRunTris strip triangles so
+// that the tile fits LDS at full occupancy.
 //
-// Memory safety on corrupted input: a meshlet whose descriptor points outside
-// the given array sizes is skipped, reuse reads are clamped into the
-// meshlet's own reuse bytes, and all LDS indices stay below T_s + 2.
+// Memory safety on corrupted input: a meshlet whose descriptor points
+// outside the given sizes (or outside the run's LDS tile) ends the run and is
+// skipped; every LDS index is bounded by the tile sizes whatever the flag
+// bits say.
 
 #include <hip/hip_runtime.h>
 
@@ -34,29 +42,34 @@ namespace gtsr {
 namespace {
 
 constexpr uint32_t kWave = 64;
-constexpr uint32_t kIdxBytes = 272;          // I[0 .. T_s+1] for T_s <= 256, padded
 constexpr uint32_t kMaxWavesPerGroup = 16;
 constexpr uint32_t kXcds = 8;                // workgroups go round-robin over 8 XCDs
 constexpr uint64_t kWorkspaceBytes = 256;
+constexpr uint32_t kRunTris = 768;           // strip triangles per run (LDS tile)
+constexpr uint32_t kRunMeshlets = 32;        // meshlets per run (one descriptor per lane)
 
-// Loads through the constant address space: a wave-uniform address becomes a
-// scalar load into SGPRs.  Only used for data the kernels never write.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef const __attribute__((address_space(4))) u32x4 const_u32x4;
-
-__device__ __forceinline__ uint4 load_uniform16(const void* p) {
-  const u32x4 v = *reinterpret_cast<const_u32x4*>(reinterpret_cast<uintptr_t>(p));
-  return make_uint4(v.x, v.y, v.z, v.w);
-}
+// One wavefront's LDS tile.
+struct RunTile {
+  static constexpr uint32_t kChunks = kRunTris / 64 + kRunMeshlets;
+  uint4 bits[kChunks];                       // LR lo/hi, INC lo/hi per chunk
+  uint32_t out[(3 * kRunTris + 3 * 64 + 8) / 4];   // + a partial chunk past the end, + shift
+  uint8_t reuse[kRunTris + 256 + 64];        // + reads by lanes whose flags say "new"
+  uint8_t idx[272];                          // I[0 .. T_s+1] of the current meshlet
+};
+constexpr uint32_t kTileBytes = sizeof(RunTile);
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Orders this wavefront's LDS writes before its later LDS reads (other lanes'
-// values); LDS operations of one wavefront complete in issue order.
+// Orders this wavefront's LDS writes before its later LDS reads of other
+// lanes' values; LDS operations of one wavefront complete in issue order.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t mask, uint32_t base) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), base));
 }
 
 struct Stream {
@@ -69,75 +82,158 @@ struct Stream {
   uint64_t out_tris;
 };
 
-// Decodes meshlet m of stream s with the calling wavefront.  I: this wave's
-// LDS index array with I[0..2] = 0,1,2 already in place.
-__device__ __forceinline__ void decode_meshlet(const Stream& s, uint32_t m, uint8_t* I, uint32_t lane) {
-  const uint4 d = load_uniform16(s.meshlets + m);
-  const uint32_t chunk_off = d.x, reuse_off = d.y, out_off = d.z;
-  const uint32_t T = d.w & 0xFFFFu, V = d.w >> 16;
-  const uint32_t nch = (T + 63) >> 6;
-  const int32_t n_ru = int32_t(T) + 2 - int32_t(V);
-  if (T - 1u >= kMaxStripTris || V < 3 || V > 256 || n_ru < 0) return;
-  if (uint64_t(chunk_off) + nch > s.chunks || uint64_t(reuse_off) + uint32_t(n_ru) > s.reuse_bytes ||
-      uint64_t(out_off) + T > s.out_tris)
-    return;
-  const uint8_t* cb = s.bits + 16ull * chunk_off;
-  const uint8_t* rb = s.reuse + reuse_off;
-  uint8_t* ob = s.out + 3ull * out_off;
+// Per-meshlet state carried from chunk to chunk (all wave-uniform).
+struct ChunkCarry {
+  uint32_t inc_base;      // 1 + increments before this chunk (triangle 0 counted as one)
+  uint32_t reuse_pos;     // reuse slots before this chunk, plus the meshlet's tile offset
+  uint32_t last_change;   // last L/R flip position in earlier chunks (0: none)
+  uint64_t prev_top;      // flag of the previous chunk's last triangle
+};
 
-  uint32_t inc_base = 2;      // 2 + increments in earlier chunks
-  uint32_t last_change = 0;   // last L/R change position in earlier chunks (0: none)
-  uint64_t prev_top = 0;      // flag of the last triangle of the previous chunk
-  for (uint32_t c = 0; c < nch; ++c) {
-    const uint4 w = load_uniform16(cb + 16ull * c);
-    const uint64_t lr = (uint64_t(w.y) << 32) | w.x;
-    uint64_t inc = (uint64_t(w.w) << 32) | w.z;
-    uint64_t ch = lr ^ ((lr << 1) | prev_top);
-    if (c == 0) { inc &= ~1ull; ch &= ~1ull; }
-
-    const uint32_t t = 64 * c + lane;
-    const bool active = t < T;
-    const uint32_t f = uint32_t(lr >> lane) & 1u;
-    const uint32_t g = uint32_t(inc >> lane) & 1u;
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(inc >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo(uint32_t(inc), 0u));
-    const uint32_t s_t = inc_base + below + g;
-    uint32_t N = s_t;
-    if (active && !g) {
-      if (t == 0) {
-        N = 2;
-      } else {
-        int32_t r = int32_t(t + 1 - s_t);
-        r = r < n_ru - 1 ? r : n_ru - 1;
-        N = r >= 0 ? rb[r] : 0u;
-      }
-    }
-    if (active && t > 0) I[t + 2] = uint8_t(N);
-
-    const uint64_t upto = ch << (63 - lane);   // change bits at or below lane t, lane t on top
-    const uint32_t piv = upto ? (t - uint32_t(__builtin_clzll(upto))) : last_change;
-
-    if (ch) last_change = 64 * c + 63 - uint32_t(__builtin_clzll(ch));
-    prev_top = lr >> 63;
-    inc_base += uint32_t(__builtin_popcountll(inc));
-
-    wave_lds_sync();
-    if (active) {
-      const uint32_t P = I[t + 1];
-      const uint32_t X = I[piv];
-      uint8_t* o = ob + 3ull * t;
-      o[0] = uint8_t(f ? P : X);
-      o[1] = uint8_t(f ? X : P);
-      o[2] = uint8_t(N);
-    }
+// Chunk C (strip triangles 64C .. 64C+63) of the meshlet whose flag chunks
+// start at tile.bits + co and whose output starts at tile byte ob.
+template <uint32_t C>
+__device__ __forceinline__ void decode_chunk(RunTile& tile, uint32_t co, uint32_t ob, uint32_t lane,
+                                             ChunkCarry& k) {
+  uint8_t* I = tile.idx;
+  const uint4 w = tile.bits[co + C];
+  const uint64_t lr = (uint64_t(uniform(w.y)) << 32) | uniform(w.x);
+  uint64_t inc = (uint64_t(uniform(w.w)) << 32) | uniform(w.z);
+  uint64_t ch = lr ^ ((lr << 1) | k.prev_top);
+  if (C == 0) {
+    inc |= 1;    // triangle 0 counts as introducing vertex 2 (I[2] = 2)
+    ch &= ~1ull;
   }
+  const uint32_t t = 64 * C + lane;
+  // new slot I[t+2]: the next vertex number, or the reuse byte whose rank is
+  // the number of reuse slots before t (lanes below minus increments below)
+  const uint32_t ones = __builtin_amdgcn_mbcnt_hi(uint32_t(inc >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(inc), 0u));
+  const uint32_t fresh = ones + k.inc_base + 1;
+  const uint32_t r = tile.reuse[(k.reuse_pos + lane) - ones];
+  const uint32_t N = __builtin_amdgcn_inverse_ballot_w64(inc) ? fresh : r;
+  I[t + 2] = uint8_t(N);
+  // pivot: the last flip at or before t
+  const uint64_t upto = ch << (63 - lane);
+  const uint32_t piv = upto ? t - uint32_t(__builtin_clzll(upto)) : k.last_change;
+
+  if (ch) k.last_change = 64 * C + 63 - uint32_t(__builtin_clzll(ch));
+  k.prev_top = lr >> 63;
+  const uint32_t news = uint32_t(__builtin_popcountll(inc));
+  k.inc_base += news;
+  k.reuse_pos += 64 - news;
+
+  wave_lds_sync();
+  const uint32_t P = I[t + 1];
+  const uint32_t X = I[piv];
+  const bool right = __builtin_amdgcn_inverse_ballot_w64(lr);
+  uint8_t* o = reinterpret_cast<uint8_t*>(tile.out) + ob + 3 * t;
+  o[0] = uint8_t(right ? P : X);
+  o[1] = uint8_t(right ? X : P);
+  o[2] = uint8_t(N);
+}
+
+// Decodes one meshlet whose flag chunks start at tile.bits[co], reuse bytes
+// at tile.reuse[ro], output at tile byte ob.  T: strip triangles (1..256).
+// Lanes past T compute garbage that lands past the meshlet's output (the next
+// meshlet overwrites it, or it lies past the run and is never stored).
+__device__ __forceinline__ void decode_meshlet(RunTile& tile, uint32_t co, uint32_t ro, uint32_t ob, uint32_t T,
+                                               uint32_t lane) {
+  ChunkCarry k{1, ro, 0, 0};
+  decode_chunk<0>(tile, co, ob, lane, k);
+  if (T > 64) decode_chunk<1>(tile, co, ob, lane, k);
+  if (T > 128) decode_chunk<2>(tile, co, ob, lane, k);
+  if (T > 192) decode_chunk<3>(tile, co, ob, lane, k);
   wave_lds_sync();
 }
 
-__device__ __forceinline__ uint8_t* wave_index_array(uint8_t* lds, uint32_t wave, uint32_t lane) {
-  uint8_t* I = lds + wave * kIdxBytes;
-  if (lane < 3) I[lane] = uint8_t(lane);
-  return I;
+// Writes tile bytes [shift, shift + bytes) to dst - shift + [shift, ...):
+// whole dwords where the dword lies inside the span, single bytes at its two
+// ragged ends.  dst is 4-byte aligned minus shift.
+__device__ __forceinline__ void store_span(uint8_t* dst_run, uint32_t bytes, const RunTile& tile, uint32_t lane) {
+  const uint32_t shift = uint32_t(reinterpret_cast<uintptr_t>(dst_run)) & 3u;
+  uint32_t* g = reinterpret_cast<uint32_t*>(dst_run - shift);
+  const uint32_t end = shift + bytes;
+  const uint32_t nd = (end + 3) >> 2;
+  for (uint32_t j = lane; j < nd; j += kWave) {
+    const uint32_t w = tile.out[j];
+    const uint32_t lo = 4 * j;
+    if (lo >= shift && lo + 4 <= end) {
+      g[j] = w;
+    } else {
+      uint8_t* gb = reinterpret_cast<uint8_t*>(g + j);
+      for (uint32_t b = 0; b < 4; ++b)
+        if (lo + b >= shift && lo + b < end) gb[b] = uint8_t(w >> (8 * b));
+    }
+  }
+}
+
+// Decodes meshlets [m, m_end) of stream s with the calling wavefront, run by
+// run.  tile.idx[0..2] must hold 0,1,2.
+__device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32_t m_end, RunTile& tile,
+                                          uint32_t lane) {
+  while (m < m_end) {
+    const uint32_t cnt = min(m_end - m, kRunMeshlets);
+    uint4 d = make_uint4(0, 0, 0, 0);
+    if (lane < cnt) d = *reinterpret_cast<const uint4*>(s.meshlets + m + lane);
+    const uint32_t T = d.w & 0xFFFFu, V = d.w >> 16;
+    const uint32_t nch = (T + 63) >> 6;
+    const uint32_t nru = T + 2 - V;
+    const uint32_t c0 = uniform(d.x), r0 = uniform(d.y), o0 = uniform(d.z);
+    const uint32_t ra = r0 & ~3u;   // reuse bytes are staged from a dword boundary
+    bool ok = lane < cnt && T - 1u < kMaxStripTris && V >= 3 && V <= 256 && V <= T + 2;
+    ok = ok && uint64_t(d.x) + nch <= s.chunks && uint64_t(d.y) + nru <= s.reuse_bytes &&
+         uint64_t(d.z) + T <= s.out_tris;
+    ok = ok && d.x - c0 + nch <= RunTile::kChunks && d.y - ra + nru <= kRunTris + 3 &&
+         d.z - o0 + T <= kRunTris && d.x >= c0 && d.y >= r0 && d.z >= o0;
+    const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
+    const uint32_t k = uint32_t(__builtin_ctzll(~okm));   // leading run of usable meshlets
+    if (k == 0) {   // the first meshlet is unusable: skip it
+      ++m;
+      continue;
+    }
+    const uint32_t c_end = __builtin_amdgcn_readlane(d.x + nch, k - 1);
+    const uint32_t r_end = __builtin_amdgcn_readlane(d.y + nru, k - 1);
+    const uint32_t o_end = __builtin_amdgcn_readlane(d.z + T, k - 1);
+
+    // stage flag chunks and reuse bytes
+    const uint4* gbits = reinterpret_cast<const uint4*>(s.bits) + c0;
+    for (uint32_t j = lane; j < c_end - c0; j += kWave) tile.bits[j] = gbits[j];
+    const uint32_t nrd = (r_end - ra + 3) >> 2;
+    uint32_t* treuse = reinterpret_cast<uint32_t*>(tile.reuse);
+    for (uint32_t j = lane; j < nrd; j += kWave) {
+      const uint64_t gofs = uint64_t(ra) + 4 * j;
+      uint32_t v;
+      if (gofs + 4 <= s.reuse_bytes) {
+        v = *reinterpret_cast<const uint32_t*>(s.reuse + gofs);
+      } else {   // the array ends inside this dword
+        v = 0;
+        for (uint32_t b = 0; b < 4; ++b)
+          if (gofs + b < s.reuse_bytes) v |= uint32_t(s.reuse[gofs + b]) << (8 * b);
+      }
+      treuse[j] = v;
+    }
+    wave_lds_sync();
+
+    uint8_t* dst = s.out + 3ull * o0;
+    const uint32_t shift = uint32_t(reinterpret_cast<uintptr_t>(dst)) & 3u;
+    for (uint32_t i = 0; i < k; ++i) {
+      const uint32_t co = __builtin_amdgcn_readlane(d.x, i) - c0;
+      const uint32_t ro = __builtin_amdgcn_readlane(d.y, i) - ra;
+      const uint32_t oo = __builtin_amdgcn_readlane(d.z, i) - o0;
+      const uint32_t Ti = __builtin_amdgcn_readlane(T, i);
+      decode_meshlet(tile, co, ro, shift + 3 * oo, Ti, lane);
+    }
+    store_span(dst, 3 * (o_end - o0), tile, lane);
+    wave_lds_sync();
+    m += k;
+  }
+}
+
+__device__ __forceinline__ RunTile& wave_tile(uint32_t wave, uint32_t lane) {
+  extern __shared__ uint4 lds_tiles[];
+  RunTile& tile = reinterpret_cast<RunTile*>(lds_tiles)[wave];
+  if (lane < 3) tile.idx[lane] = uint8_t(lane);
+  return tile;
 }
 
 // Plain decoder: workgroup b covers waves_per_group * mpw consecutive
@@ -148,20 +244,17 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
     const gtsr_meshlet* __restrict__ meshlets, const uint8_t* __restrict__ bits,
     const uint8_t* __restrict__ reuse, uint8_t* __restrict__ out, uint32_t meshlet_count,
     uint64_t chunks, uint64_t reuse_bytes, uint64_t out_tris, uint32_t mpw) {
-  extern __shared__ uint8_t lds[];
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = uniform(threadIdx.x / kWave);
   const uint32_t waves = blockDim.x / kWave;
-  uint8_t* I = wave_index_array(lds, wave, lane);
+  RunTile& tile = wave_tile(wave, lane);
   const uint32_t per_xcd = gridDim.x / kXcds;
-  const uint32_t tile = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-  const uint64_t m0 = (uint64_t(tile) * waves + wave) * mpw;
+  const uint32_t group = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+  const uint64_t m0 = (uint64_t(group) * waves + wave) * mpw;
+  if (m0 >= meshlet_count) return;
+  const uint32_t m1 = uint32_t(min(m0 + mpw, uint64_t(meshlet_count)));
   const Stream s{meshlets, bits, reuse, out, chunks, reuse_bytes, out_tris};
-  for (uint32_t k = 0; k < mpw; ++k) {
-    const uint64_t m = m0 + k;
-    if (m >= meshlet_count) break;
-    decode_meshlet(s, uint32_t(m), I, lane);
-  }
+  decode_range(s, uint32_t(m0), m1, tile, lane);
 }
 
 // Persistent batched decoder: every wavefront takes work items (a run of
@@ -169,33 +262,30 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
     const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
     const gtsr_work_item* __restrict__ work, uint32_t work_items, uint32_t* __restrict__ counter) {
-  extern __shared__ uint8_t lds[];
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = uniform(threadIdx.x / kWave);
-  uint8_t* I = wave_index_array(lds, wave, lane);
+  RunTile& tile = wave_tile(wave, lane);
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = atomicAdd(counter, 1u);
     item = uniform(item);
     if (item >= work_items) break;
-    const uint4 wi = load_uniform16(work + item);
-    if (wi.x >= mesh_count) continue;
-    const gtsr_mesh_entry* e = table + wi.x;
-    const uint4 e0 = load_uniform16(reinterpret_cast<const uint8_t*>(e));
-    const uint4 e1 = load_uniform16(reinterpret_cast<const uint8_t*>(e) + 16);
-    const uint4 e2 = load_uniform16(reinterpret_cast<const uint8_t*>(e) + 32);
-    const uint4 e3 = load_uniform16(reinterpret_cast<const uint8_t*>(e) + 48);
+    const gtsr_work_item wi = work[item];
+    const uint32_t mesh = uniform(wi.mesh);
+    if (mesh >= mesh_count) continue;
+    const gtsr_mesh_entry& e = table[mesh];
     Stream s;
-    s.meshlets = reinterpret_cast<const gtsr_meshlet*>((uint64_t(e0.y) << 32) | e0.x);
-    s.bits = reinterpret_cast<const uint8_t*>((uint64_t(e0.w) << 32) | e0.z);
-    s.reuse = reinterpret_cast<const uint8_t*>((uint64_t(e1.y) << 32) | e1.x);
-    s.out = reinterpret_cast<uint8_t*>((uint64_t(e1.w) << 32) | e1.z);
-    const uint32_t mcount = e2.x;
-    s.chunks = ((uint64_t(e2.w) << 32) | e2.z) / 16;
-    s.reuse_bytes = (uint64_t(e3.y) << 32) | e3.x;
-    s.out_tris = (uint64_t(e3.w) << 32) | e3.z;
-    const uint32_t end = wi.z < mcount ? wi.z : mcount;
-    for (uint32_t m = wi.y; m < end; ++m) decode_meshlet(s, m, I, lane);
+    s.meshlets = e.meshlets;
+    s.bits = e.bits;
+    s.reuse = e.reuse;
+    s.out = e.out;
+    s.chunks = e.bits_bytes / 16;
+    s.reuse_bytes = e.reuse_bytes;
+    s.out_tris = e.strip_triangles;
+    const uint32_t mcount = e.meshlet_count;
+    const uint32_t first = uniform(wi.first);
+    const uint32_t end = min(uniform(wi.end), mcount);
+    if (first < end) decode_range(s, first, end, tile, lane);
   }
 }
 
@@ -205,7 +295,7 @@ __global__ void k_fill_zero(uint32_t* p, uint32_t n) {
 }
 
 struct Defaults {
-  uint32_t waves = 4, mpw = 4, gpc = 8;
+  uint32_t waves = 4, mpw = 16, gpc = 8;
 };
 
 int resolve_cfg(const gtsr_launch_cfg* cfg, Defaults& d, const char* who) {
@@ -266,7 +356,7 @@ int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gts
   if (int rc = check_launch(who)) return rc;
   uint32_t groups = cus * d.gpc;
   groups = (groups + kXcds - 1) / kXcds * kXcds;
-  hipLaunchKernelGGL(k_decode_batched, dim3(groups), dim3(kWave * d.waves), d.waves * kIdxBytes, stream,
+  hipLaunchKernelGGL(k_decode_batched, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes, stream,
                      table, mesh_count, work, work_items, counter);
   return check_launch(who);
 }
@@ -299,7 +389,7 @@ void launch_plain(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, 
   const uint64_t per_group = uint64_t(d.waves) * d.mpw;
   uint64_t groups = (dev->meshlet_count + per_group - 1) / per_group;
   groups = (groups + kXcds - 1) / kXcds * kXcds;
-  hipLaunchKernelGGL(k_decode_plain, dim3(uint32_t(groups)), dim3(kWave * d.waves), d.waves * kIdxBytes,
+  hipLaunchKernelGGL(k_decode_plain, dim3(uint32_t(groups)), dim3(kWave * d.waves), d.waves * kTileBytes,
                      stream, dev->meshlets, dev->bits, dev->reuse, dev_out, dev->meshlet_count,
                      dev->bits_bytes / 16, dev->reuse_bytes, out_bytes / 3, d.mpw);
 }
