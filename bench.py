@@ -144,12 +144,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", choices=["batched", "sphere"], default="batched")
     ap.add_argument("--meshes", type=int, default=2000)
-    ap.add_argument("--target-tris", type=int, default=2048)
+    ap.add_argument("--target-tris", type=int, default=768)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--groups-per-cu", type=int, default=0)
     ap.add_argument("--meshlets-per-wave", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-mesh", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (a known-size "
+                         "kernel for scaling hardware traffic counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -222,6 +225,16 @@ def main():
         # leave the batched result in pool.out for the baseline comparison
         step()
         torch.cuda.synchronize()
+
+    if args.calib_copy_mib:
+        nbytes = args.calib_copy_mib << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
 
     achieved = alg / (ms / 1e3) / 1e9
     traffic = read_traffic(kernel, args.workload)

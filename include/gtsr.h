@@ -110,8 +110,8 @@ typedef struct gtsr_stream {
 /* Launch shape for the decoders; NULL selects the built-in defaults. */
 typedef struct gtsr_launch_cfg {
   uint32_t waves_per_group;     /* 1..16: workgroup of 64*waves threads */
-  uint32_t meshlets_per_wave;   /* decode_meshlets: consecutive meshlets per wave, 1..64 */
-  uint32_t groups_per_cu;       /* decode_meshlets_batched: resident groups per CU, 1..32 */
+  uint32_t meshlets_per_wave;   /* decode_meshlets: meshlets per wavefront at least, 1..1024 */
+  uint32_t groups_per_cu;       /* groups per CU the grid is capped at, 1..32 */
   uint32_t reserved;            /* must be 0 */
 } gtsr_launch_cfg;
 
@@ -174,10 +174,13 @@ int gtsr_plan_batch(const gtsr_meshlet* const* host_meshlets, const uint32_t* me
 
 /* ---------------------------------------------------------------- GPU side */
 
-/* Decode one mesh on the GPU (Sec. 4.2 / 4.3): one wavefront per run of
- * consecutive meshlets, one lane per strip triangle.  dev: host struct
+/* Decode one mesh on the GPU (Sec. 4.2 / 4.3): each wavefront decodes a
+ * contiguous block of meshlets, one lane per strip triangle.  dev: host struct
  * holding device pointers.  dev_out: device, out_bytes >= 3 *
- * strip_triangles.  dev->meshlets and dev->bits must be 16-byte aligned.
+ * strip_triangles.  dev->meshlets, dev->bits and dev->reuse must be 16-byte
+ * aligned, and the reuse allocation must extend to the next multiple of 16
+ * bytes past reuse_bytes (it is read in whole 16-byte blocks); the output may
+ * have any alignment.
  * Enqueued on hip_stream (a hipStream_t; NULL = the null stream); returns
  * before the work finishes; allocates nothing, never synchronizes.  Meshlets whose descriptor points outside the given sizes
  * are skipped (their output bytes are left untouched); gtsr_validate reports
@@ -200,28 +203,25 @@ int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_ou
 
 /* Decode many meshes in one persistent launch.  dev_mesh_table: device
  * gtsr_mesh_entry[mesh_count]; dev_work: device gtsr_work_item[work_items]
- * (gtsr_plan_batch); both 16-byte aligned, as is every entry's meshlets and
- * bits pointer.  Waves pull work items through a counter in
- * dev_workspace (device, >= gtsr_batched_workspace_bytes(), 256-byte
- * aligned), which this call clears with a fill kernel before the decode
- * kernel (no memset node, so the pair may be captured in a graph).  Calls
- * sharing a workspace must not overlap.  Same skipping rule as
- * decode_meshlets; work items naming a mesh >= mesh_count are skipped.
- * Errors: EINVAL, EHIP. */
+ * (gtsr_plan_batch); both 16-byte aligned, as must be every entry's
+ * meshlets, bits and reuse pointer (entries that are not are skipped); each
+ * reuse allocation must extend to a multiple of 16 bytes (as for
+ * decode_meshlets).  The grid is sized to stay resident (groups_per_cu groups on
+ * every CU); each wavefront decodes one contiguous block of the work list,
+ * so the list should be balanced by strip triangles (gtsr_plan_batch) and
+ * have many more items than the grid has wavefronts.  No atomics, no
+ * scratch memory.  Same skipping rule as decode_meshlets; items naming a
+ * mesh >= mesh_count are skipped.  Errors: EINVAL, EHIP. */
 int decode_meshlets_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
                             const gtsr_work_item* dev_work, uint32_t work_items,
-                            void* dev_workspace, uint64_t workspace_bytes,
                             const gtsr_launch_cfg* cfg, void* hip_stream);
 
-uint64_t gtsr_batched_workspace_bytes(void);
-
-/* Capture decode_meshlets_batched (fill kernel + decode kernel) into an
- * executable HIP graph once; *graph_exec receives the handle.  The tables and
- * workspace must stay valid while the graph is used; their contents may
- * change between launches, their addresses may not.  Errors: EINVAL, EHIP. */
+/* Capture decode_meshlets_batched into an executable HIP graph once;
+ * *graph_exec receives the handle.  The tables must stay valid while the
+ * graph is used; their contents may change between launches, their
+ * addresses and sizes may not.  Errors: EINVAL, EHIP. */
 int gtsr_batched_graph_create(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
                               const gtsr_work_item* dev_work, uint32_t work_items,
-                              void* dev_workspace, uint64_t workspace_bytes,
                               const gtsr_launch_cfg* cfg, void** graph_exec);
 
 /* Enqueue a captured graph on hip_stream.  Errors: EINVAL, EHIP. */

@@ -22,8 +22,7 @@ OK, EINVAL, ENOMEM, EDEGENERATE, ELIMIT, ECORRUPT, EHIP = 0, -1, -2, -3, -4, -5,
 EXPORTED = (
     "encode_meshlets", "gtsr_encoded_view_get", "gtsr_encoded_free", "gtsr_validate",
     "gtsr_plan_batch", "decode_meshlets", "gtsr_decode_meshlets_cfg", "gtsr_decode_meshlets_many",
-    "decode_meshlets_batched",
-    "gtsr_batched_workspace_bytes", "gtsr_batched_graph_create", "gtsr_graph_launch",
+    "decode_meshlets_batched", "gtsr_batched_graph_create", "gtsr_graph_launch",
     "gtsr_graph_destroy", "gtsr_device_cu_count", "gtsr_last_error",
 )
 
@@ -96,10 +95,8 @@ def lib():
         "decode_meshlets": (C.c_int, [C.POINTER(StreamDesc), vp, u64, vp]),
         "gtsr_decode_meshlets_cfg": (C.c_int, [C.POINTER(StreamDesc), vp, u64, C.POINTER(LaunchCfg), vp]),
         "gtsr_decode_meshlets_many": (C.c_int, [vp, vp, vp, u32, C.POINTER(LaunchCfg), vp]),
-        "decode_meshlets_batched": (C.c_int, [vp, u32, vp, u32, vp, u64, C.POINTER(LaunchCfg), vp]),
-        "gtsr_batched_workspace_bytes": (u64, []),
-        "gtsr_batched_graph_create": (C.c_int, [vp, u32, vp, u32, vp, u64, C.POINTER(LaunchCfg),
-                                                C.POINTER(vp)]),
+        "decode_meshlets_batched": (C.c_int, [vp, u32, vp, u32, C.POINTER(LaunchCfg), vp]),
+        "gtsr_batched_graph_create": (C.c_int, [vp, u32, vp, u32, C.POINTER(LaunchCfg), C.POINTER(vp)]),
         "gtsr_graph_launch": (C.c_int, [vp, vp]),
         "gtsr_graph_destroy": (None, [vp]),
         "gtsr_device_cu_count": (u32, []),
@@ -261,17 +258,23 @@ class DeviceStream:
         return self.meshlets.numel() + self.bits.numel() + self.reuse.numel()
 
 
-def to_device(enc: Encoded, device="cuda") -> DeviceStream:
+def upload_padded(a: np.ndarray, device="cuda"):
+    """A uint8 device copy of ``a`` whose allocation is padded with zeros to a
+    multiple of 16 bytes (the decoders read reuse bytes in 16-byte blocks);
+    the returned tensor has ``a``'s length."""
     torch = _torch()
+    flat = np.ascontiguousarray(a).view(np.uint8).reshape(-1)
+    n = flat.size
+    buf = torch.zeros((n + 15) // 16 * 16 + 16, dtype=torch.uint8, device=device)
+    if n:
+        buf[:n].copy_(torch.from_numpy(flat))
+    return buf[:n]
 
-    def up(a):
-        t = torch.from_numpy(np.ascontiguousarray(a).view(np.uint8).reshape(-1))
-        if t.numel() == 0:
-            return torch.zeros(16, dtype=torch.uint8, device=device)[:0]
-        return t.to(device)
 
-    return DeviceStream(up(enc.meshlets), up(enc.bits), up(enc.reuse), enc.meshlet_count,
-                        enc.strip_triangles, int(enc.stats.get("input_triangles", 0)))
+def to_device(enc: Encoded, device="cuda") -> DeviceStream:
+    return DeviceStream(upload_padded(enc.meshlets, device), upload_padded(enc.bits, device),
+                        upload_padded(enc.reuse, device), enc.meshlet_count, enc.strip_triangles,
+                        int(enc.stats.get("input_triangles", 0)))
 
 
 def decode(ds: DeviceStream, out=None, stream=None, cfg=None):
@@ -289,10 +292,10 @@ def decode(ds: DeviceStream, out=None, stream=None, cfg=None):
 class Batch:
     """Many device-resident meshes decoded by one persistent launch.
 
-    Holds the device mesh table, the work list, the workspace and one output
+    Holds the device mesh table, the work list and one output
     tensor per mesh (views into a single allocation)."""
 
-    def __init__(self, streams, target_tris: int = 2048, host_meshlets=None, device="cuda", outs=None):
+    def __init__(self, streams, target_tris: int = 768, host_meshlets=None, device="cuda", outs=None):
         torch = _torch()
         self.streams = list(streams)
         n = len(self.streams)
@@ -315,16 +318,13 @@ class Batch:
         items = plan_batch(host_meshlets, target_tris)
         self.work_items = int(items.shape[0])
         self.work = torch.from_numpy(items.view(np.uint8).reshape(-1).copy()).to(device)
-        ws = int(lib().gtsr_batched_workspace_bytes())
-        self.workspace = torch.zeros(ws, dtype=torch.uint8, device=device)
         self.mesh_count = n
         self._graphs = []
 
     def launch(self, stream=None, cfg=None):
         L = lib()
         _check(L.decode_meshlets_batched(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
-                                         self.work_items, self.workspace.data_ptr(),
-                                         self.workspace.numel(), _cfg(cfg), _stream_handle(stream)))
+                                         self.work_items, _cfg(cfg), _stream_handle(stream)))
         return self.outs
 
     def graph(self, cfg=None):
@@ -332,8 +332,7 @@ class Batch:
         L = lib()
         h = C.c_void_p()
         _check(L.gtsr_batched_graph_create(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
-                                           self.work_items, self.workspace.data_ptr(),
-                                           self.workspace.numel(), _cfg(cfg), C.byref(h)))
+                                           self.work_items, _cfg(cfg), C.byref(h)))
         g = Graph(h)
         self._graphs.append(g)
         return g
@@ -425,8 +424,6 @@ class Pool:
         self.out_bytes = (C.c_uint64 * max(n, 1))(*[int(x) for x in 3 * self.strip_tris])
         self.work = None
         self.work_items = 0
-        self.workspace = torch.zeros(int(lib().gtsr_batched_workspace_bytes()), dtype=torch.uint8,
-                                     device=device)
         self._graphs = []
 
     def output(self, i: int):
@@ -434,7 +431,7 @@ class Pool:
         a, b = int(self.out_offsets[i]), int(self.out_offsets[i + 1])
         return self.out[a:b].view(-1, 3)
 
-    def plan(self, target_tris: int = 2048):
+    def plan(self, target_tris: int = 768):
         torch = _torch()
         items = plan_batch(self.host_meshlets, target_tris)
         self.work_items = int(items.shape[0])
@@ -446,16 +443,14 @@ class Pool:
         if self.work is None:
             self.plan()
         _check(lib().decode_meshlets_batched(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
-                                             self.work_items, self.workspace.data_ptr(),
-                                             self.workspace.numel(), _cfg(cfg), _stream_handle(stream)))
+                                             self.work_items, _cfg(cfg), _stream_handle(stream)))
 
     def batched_graph(self, cfg=None):
         if self.work is None:
             self.plan()
         h = C.c_void_p()
         _check(lib().gtsr_batched_graph_create(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
-                                               self.work_items, self.workspace.data_ptr(),
-                                               self.workspace.numel(), _cfg(cfg), C.byref(h)))
+                                               self.work_items, _cfg(cfg), C.byref(h)))
         g = Graph(h)
         self._graphs.append(g)
         return g

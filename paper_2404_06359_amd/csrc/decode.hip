@@ -18,18 +18,24 @@
 //                 change carried from earlier chunks (fans longer than a word).
 //   triangle      f[t] = L: (X_t, I[t+1], I[t+2]);  R: (I[t+1], X_t, I[t+2]).
 //
-// Data movement.  A wavefront decodes a run of consecutive meshlets of one
-// mesh: it loads up to 32 descriptors with one vector load, stages the run's
-// flag chunks and reuse bytes in LDS with coalesced loads, decodes each
-// meshlet from LDS into an LDS output tile, then writes the run's output
-// bytes (contiguous in the stream layout) with dword stores.  The chunk loop
-// touches no global memory.  A run holds at most kRunTris strip triangles so
-// that the tile fits LDS at full occupancy.
+// Data movement.  A wavefront decodes a contiguous block of meshlets of one
+// mesh, run by run (a run: at most 32 meshlets and kRunTris strip
+// triangles, contiguous in all three stream arrays and in the output).  Per
+// run it loads the descriptors with one vector load, the flag chunks into
+// VGPRs (one chunk per lane) and the reuse bytes into LDS, decodes every
+// meshlet from LDS into an LDS output tile, and writes the run's output span
+// with 16-byte stores.  The runs are software-pipelined: while run j is
+// decoded, the flag chunks and reuse bytes of run j+1 and the descriptors of
+// run j+2 are already in flight.  All global loads and stores are raw buffer
+// operations whose inactive lanes carry an out-of-range offset (reads return
+// zero, writes are dropped), so every run issues the same instructions and
+// waiting for the prefetched loads never waits for the previous run's stores.
 //
-// Memory safety on corrupted input: a meshlet whose descriptor points
-// outside the given sizes (or outside the run's LDS tile) ends the run and is
-// skipped; every LDS index is bounded by the tile sizes whatever the flag
-// bits say.
+// Memory safety on corrupted input: a meshlet whose descriptor points outside
+// the given sizes, does not continue its predecessor contiguously, or does
+// not fit the run's tile ends the run and is skipped; buffer ranges bound
+// every global access; every LDS index is bounded by the tile sizes whatever
+// the flag bits say.
 
 #include <hip/hip_runtime.h>
 
@@ -44,21 +50,34 @@ namespace {
 constexpr uint32_t kWave = 64;
 constexpr uint32_t kMaxWavesPerGroup = 16;
 constexpr uint32_t kXcds = 8;                // workgroups go round-robin over 8 XCDs
-constexpr uint64_t kWorkspaceBytes = 256;
-constexpr uint32_t kRunTris = 768;           // strip triangles per run (LDS tile)
+constexpr uint32_t kRunTris = 1024;          // strip triangles per run (LDS tile)
 constexpr uint32_t kRunMeshlets = 32;        // meshlets per run (one descriptor per lane)
+constexpr uint32_t kRunChunks = kRunTris / 64 + kRunMeshlets;   // flag chunks per run (one per lane)
+constexpr uint32_t kReuseStage = 16 * kWave;                    // reuse bytes staged per run
+constexpr uint32_t kOutBlocks = (3 * kRunTris + 3 * 64 + 16 + 15) / 16;
+static_assert(kRunChunks <= kWave, "one flag chunk per lane");
+static_assert(kRunTris <= kReuseStage, "reuse bytes of a run fit one 16-byte block per lane (the plan also caps them)");
+static_assert(kOutBlocks <= 4 * kWave, "four 16-byte stores per lane cover the output tile");
 
 // One wavefront's LDS tile.
 struct RunTile {
-  static constexpr uint32_t kChunks = kRunTris / 64 + kRunMeshlets;
-  uint4 bits[kChunks];                       // LR lo/hi, INC lo/hi per chunk
-  uint32_t out[(3 * kRunTris + 3 * 64 + 8) / 4];   // + a partial chunk past the end, + shift
-  uint8_t reuse[kRunTris + 256 + 64];        // + reads by lanes whose flags say "new"
+  uint4 out[kOutBlocks];                     // + a partial chunk past the run, + 16-byte shift
+  uint8_t reuse[kReuseStage + 64];           // + reads by lanes whose flags say "new"
   uint8_t idx[272];                          // I[0 .. T_s+1] of the current meshlet
 };
 constexpr uint32_t kTileBytes = sizeof(RunTile);
 
-__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+// The lane builtins return int; these keep every value unsigned (a signed
+// value widened into a 64-bit flag word would smear its sign bit upward).
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return uint32_t(__builtin_amdgcn_readfirstlane(v)); }
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t lane) {
+  return uint32_t(__builtin_amdgcn_readlane(v, lane));
+}
+
+// Value of the lane below (lane 0 gets 0): DPP wavefront shift right by one.
+__device__ __forceinline__ uint32_t from_lane_below(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138, 0xF, 0xF, false));
+}
 
 // Orders this wavefront's LDS writes before its later LDS reads of other
 // lanes' values; LDS operations of one wavefront complete in issue order.
@@ -68,234 +87,383 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t mbcnt64(uint64_t mask, uint32_t base) {
-  return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), base));
+// Raw buffer resources: base + byte range; accesses at offsets past the range
+// read zero / write nothing.
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr uint32_t kOutOfRange = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), kRsrcWord3);
+}
+
+__device__ __forceinline__ uint4 load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, int(off), 0, 0));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void store16(__amdgpu_buffer_rsrc_t r, uint32_t off, const uint4& w) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 v = {w.x, w.y, w.z, w.w};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, int(off), 0, 0);
 }
 
 struct Stream {
-  const gtsr_meshlet* meshlets;
+  const uint8_t* meshlets;
   const uint8_t* bits;
   const uint8_t* reuse;
   uint8_t* out;
-  uint64_t chunks;
-  uint64_t reuse_bytes;
-  uint64_t out_tris;
+  uint32_t chunks;        // the array sizes, clipped to 32 bits (offsets are 32-bit)
+  uint32_t reuse_bytes;
+  uint32_t out_tris;
 };
 
-// Per-meshlet state carried from chunk to chunk (all wave-uniform).
-struct ChunkCarry {
-  uint32_t inc_base;      // 1 + increments before this chunk (triangle 0 counted as one)
-  uint32_t reuse_pos;     // reuse slots before this chunk, plus the meshlet's tile offset
-  uint32_t last_change;   // last L/R flip position in earlier chunks (0: none)
-  uint64_t prev_top;      // flag of the previous chunk's last triangle
+__device__ __forceinline__ uint32_t clip32(uint64_t v) { return v > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(v); }
+
+// ---------------------------------------------------------------- one meshlet
+
+// Flag words of one chunk, wave-uniform (SGPRs).
+struct Flags {
+  uint64_t lr, inc;
 };
 
-// Chunk C (strip triangles 64C .. 64C+63) of the meshlet whose flag chunks
-// start at tile.bits + co and whose output starts at tile byte ob.
+__device__ __forceinline__ Flags chunk_flags(const uint4& bv, uint32_t idx) {
+  Flags f;
+  f.lr = (uint64_t(lane_value(bv.y, idx)) << 32) | lane_value(bv.x, idx);
+  f.inc = (uint64_t(lane_value(bv.w, idx)) << 32) | lane_value(bv.z, idx);
+  return f;
+}
+
+// Per-lane LDS pointers, fixed for the kernel.
+struct LanePtrs {
+  const uint8_t* reuse;   // tile.reuse + lane
+  uint8_t* idx;           // tile.idx + lane
+  uint8_t* out;           // tile.out + 3 * lane
+};
+
+// Phase 1 for chunk C: the new slot I[t+2] -- the next vertex number, or the
+// reuse byte whose rank is the number of reuse slots before t (lanes below
+// minus increments below).  inc_base: 2 + increments before this chunk,
+// triangle 0 counted as introducing vertex 2; reuse_pos: reuse slots before
+// this chunk plus the meshlet's tile offset.
 template <uint32_t C>
-__device__ __forceinline__ void decode_chunk(RunTile& tile, uint32_t co, uint32_t ob, uint32_t lane,
-                                             ChunkCarry& k) {
-  uint8_t* I = tile.idx;
-  const uint4 w = tile.bits[co + C];
-  const uint64_t lr = (uint64_t(uniform(w.y)) << 32) | uniform(w.x);
-  uint64_t inc = (uint64_t(uniform(w.w)) << 32) | uniform(w.z);
-  uint64_t ch = lr ^ ((lr << 1) | k.prev_top);
-  if (C == 0) {
-    inc |= 1;    // triangle 0 counts as introducing vertex 2 (I[2] = 2)
-    ch &= ~1ull;
-  }
-  const uint32_t t = 64 * C + lane;
-  // new slot I[t+2]: the next vertex number, or the reuse byte whose rank is
-  // the number of reuse slots before t (lanes below minus increments below)
+__device__ __forceinline__ uint32_t new_index(const LanePtrs& lp, const Flags& f, uint32_t& inc_base,
+                                              uint32_t& reuse_pos) {
+  const uint64_t inc = C == 0 ? (f.inc | 1) : f.inc;
   const uint32_t ones = __builtin_amdgcn_mbcnt_hi(uint32_t(inc >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(inc), 0u));
-  const uint32_t fresh = ones + k.inc_base + 1;
-  const uint32_t r = tile.reuse[(k.reuse_pos + lane) - ones];
+  const uint32_t fresh = ones + inc_base;
+  const uint32_t r = lp.reuse[reuse_pos - ones];
   const uint32_t N = __builtin_amdgcn_inverse_ballot_w64(inc) ? fresh : r;
-  I[t + 2] = uint8_t(N);
-  // pivot: the last flip at or before t
-  const uint64_t upto = ch << (63 - lane);
-  const uint32_t piv = upto ? t - uint32_t(__builtin_clzll(upto)) : k.last_change;
-
-  if (ch) k.last_change = 64 * C + 63 - uint32_t(__builtin_clzll(ch));
-  k.prev_top = lr >> 63;
+  lp.idx[64 * C + 2] = uint8_t(N);
   const uint32_t news = uint32_t(__builtin_popcountll(inc));
-  k.inc_base += news;
-  k.reuse_pos += 64 - news;
+  inc_base += news;
+  reuse_pos += 64 - news;
+  return N;
+}
 
-  wave_lds_sync();
-  const uint32_t P = I[t + 1];
-  const uint32_t X = I[piv];
-  const bool right = __builtin_amdgcn_inverse_ballot_w64(lr);
-  uint8_t* o = reinterpret_cast<uint8_t*>(tile.out) + ob + 3 * t;
+// Phase 2 for chunk C: pivot (the last L/R flip at or before t) and the
+// oriented triple, written at out_m + 3t.  In chunk 0 the change word gets
+// bit 0 set: "no flip so far" then lands on position 0, whose vertex I[0] is
+// the right pivot.
+template <uint32_t C>
+__device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t* idx0, uint8_t* out_m,
+                                              const Flags& f, uint32_t N, uint32_t lane, uint32_t& last_change,
+                                              uint64_t& prev_top) {
+  uint64_t ch = f.lr ^ ((f.lr << 1) | prev_top);
+  if (C == 0) ch |= 1;
+  const uint64_t upto = ch << (63 - lane);
+  const uint8_t* at_t = lp.idx + 64 * C;                  // &I[t]
+  const uint8_t* px = at_t - __builtin_clzll(upto);       // &I[last flip <= t] when upto != 0
+  if (C != 0 && !upto) px = idx0 + last_change;
+  if (C == 0 || ch) last_change = 64 * C + 63 - uint32_t(__builtin_clzll(ch));   // else: no flip in this chunk
+  prev_top = f.lr >> 63;
+  const uint32_t P = at_t[1];
+  const uint32_t X = *px;
+  const bool right = __builtin_amdgcn_inverse_ballot_w64(f.lr);
+  uint8_t* o = out_m + 192 * C;
   o[0] = uint8_t(right ? P : X);
   o[1] = uint8_t(right ? X : P);
   o[2] = uint8_t(N);
 }
 
-// Decodes one meshlet whose flag chunks start at tile.bits[co], reuse bytes
-// at tile.reuse[ro], output at tile byte ob.  T: strip triangles (1..256).
-// Lanes past T compute garbage that lands past the meshlet's output (the next
-// meshlet overwrites it, or it lies past the run and is never stored).
-__device__ __forceinline__ void decode_meshlet(RunTile& tile, uint32_t co, uint32_t ro, uint32_t ob, uint32_t T,
-                                               uint32_t lane) {
-  ChunkCarry k{1, ro, 0, 0};
-  decode_chunk<0>(tile, co, ob, lane, k);
-  if (T > 64) decode_chunk<1>(tile, co, ob, lane, k);
-  if (T > 128) decode_chunk<2>(tile, co, ob, lane, k);
-  if (T > 192) decode_chunk<3>(tile, co, ob, lane, k);
+// Decodes one meshlet of NCH flag chunks (in lanes co.. of bv), reuse bytes
+// at tile.reuse[ro], output at tile byte ob.  Phase 1 writes the index slots
+// of all chunks, phase 2 reads them back, so each meshlet waits for LDS twice
+// whatever its size.  Lanes past T_s compute garbage that lands past the
+// meshlet's output (the next meshlet overwrites it, or it lies past the run
+// and is never stored).
+template <uint32_t NCH>
+__device__ __forceinline__ void decode_meshlet(RunTile& tile, const LanePtrs& lp, const uint4& bv, uint32_t co,
+                                               uint32_t ro, uint32_t ob, uint32_t lane) {
+  Flags f0 = chunk_flags(bv, co), f1{0, 0}, f2{0, 0}, f3{0, 0};
+  if constexpr (NCH > 1) f1 = chunk_flags(bv, co + 1);
+  if constexpr (NCH > 2) f2 = chunk_flags(bv, co + 2);
+  if constexpr (NCH > 3) f3 = chunk_flags(bv, co + 3);
+  uint32_t inc_base = 2, reuse_pos = ro;
+  const uint32_t n0 = new_index<0>(lp, f0, inc_base, reuse_pos);
+  uint32_t n1 = 0, n2 = 0, n3 = 0;
+  if constexpr (NCH > 1) n1 = new_index<1>(lp, f1, inc_base, reuse_pos);
+  if constexpr (NCH > 2) n2 = new_index<2>(lp, f2, inc_base, reuse_pos);
+  if constexpr (NCH > 3) n3 = new_index<3>(lp, f3, inc_base, reuse_pos);
+  wave_lds_sync();
+  uint8_t* out_m = lp.out + ob;
+  uint32_t last_change = 0;
+  uint64_t prev_top = 0;
+  emit_triangle<0>(lp, tile.idx, out_m, f0, n0, lane, last_change, prev_top);
+  if constexpr (NCH > 1) emit_triangle<1>(lp, tile.idx, out_m, f1, n1, lane, last_change, prev_top);
+  if constexpr (NCH > 2) emit_triangle<2>(lp, tile.idx, out_m, f2, n2, lane, last_change, prev_top);
+  if constexpr (NCH > 3) emit_triangle<3>(lp, tile.idx, out_m, f3, n3, lane, last_change, prev_top);
   wave_lds_sync();
 }
 
-// Writes tile bytes [shift, shift + bytes) to dst - shift + [shift, ...):
-// whole dwords where the dword lies inside the span, single bytes at its two
-// ragged ends.  dst is 4-byte aligned minus shift.
-__device__ __forceinline__ void store_span(uint8_t* dst_run, uint32_t bytes, const RunTile& tile, uint32_t lane) {
-  const uint32_t shift = uint32_t(reinterpret_cast<uintptr_t>(dst_run)) & 3u;
-  uint32_t* g = reinterpret_cast<uint32_t*>(dst_run - shift);
-  const uint32_t end = shift + bytes;
-  const uint32_t nd = (end + 3) >> 2;
-  for (uint32_t j = lane; j < nd; j += kWave) {
-    const uint32_t w = tile.out[j];
-    const uint32_t lo = 4 * j;
-    if (lo >= shift && lo + 4 <= end) {
-      g[j] = w;
+// --------------------------------------------------------------------- runs
+
+// A run: the first k meshlets of a descriptor batch (k = 0: the batch's first
+// meshlet is unusable and is skipped).  All fields wave-uniform.
+struct Plan {
+  uint32_t k;
+  uint32_t c0, r0, o0;    // first flag chunk, reuse byte, output triangle
+  uint32_t nch;           // flag chunks
+  uint32_t ra, nrb;       // reuse staging start (16-byte aligned) and 16-byte blocks
+  uint32_t tris;          // strip triangles
+};
+
+// Per-lane layout of meshlet `lane` in the run's tile, one word:
+// bits 0..5 first flag chunk, 6..16 reuse offset, 17..28 output triangle
+// offset (triangles, < 4096), 29..30 chunk count - 1.
+__device__ __forceinline__ uint32_t pack_layout(uint32_t co, uint32_t ro, uint32_t ot, uint32_t nch) {
+  return co | (ro << 6) | (ot << 17) | ((nch - 1) << 29);
+}
+static_assert(kRunChunks <= 64 && kReuseStage + 64 <= 2048 && kRunTris < 4096, "layout fields fit");
+
+// Descriptors of meshlets [m, min(m + 32, m_end)), one per lane (zero past).
+__device__ __forceinline__ uint4 load_descriptors(const Stream& s, uint32_t m, uint32_t m_end, uint32_t lane) {
+  const uint32_t cnt = m < m_end ? min(m_end - m, kRunMeshlets) : 0u;
+  return load16(buffer(s.meshlets + 16ull * m, 16 * cnt), 16 * lane);
+}
+
+__device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, uint32_t m, uint32_t m_end, uint32_t lane,
+                                          uint32_t& layout) {
+  const uint32_t cnt = m < m_end ? min(m_end - m, kRunMeshlets) : 0u;
+  const uint32_t T = d.w & 0xFFFFu, V = d.w >> 16;
+  const uint32_t nch = (T + 63) >> 6;
+  const uint32_t nru = T + 2 - V;
+  Plan p;
+  p.c0 = uniform(d.x);
+  p.r0 = uniform(d.y);
+  p.o0 = uniform(d.z);
+  p.ra = p.r0 & ~15u;
+  // counts in range, arrays not overrun (overflow-free forms)
+  bool ok = lane < cnt && T - 1u < kMaxStripTris && V >= 3 && V <= 256 && V <= T + 2;
+  ok = ok && d.x <= s.chunks && nch <= s.chunks - d.x && d.y <= s.reuse_bytes && nru <= s.reuse_bytes - d.y &&
+       d.z <= s.out_tris && T <= s.out_tris - d.z;
+  // contiguous with the meshlet before it (lane 0 starts the run)
+  const uint32_t ex = d.x + nch, ey = d.y + nru, ez = d.z + T;
+  const uint32_t px = from_lane_below(ex), py = from_lane_below(ey), pz = from_lane_below(ez);
+  ok = ok && (lane == 0 || (d.x == px && d.y == py && d.z == pz));
+  // the run still fits the tile
+  ok = ok && ex - p.c0 <= kRunChunks && ey - p.ra <= kReuseStage && ez - p.o0 <= kRunTris;
+  const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
+  p.k = uint32_t(__builtin_ctzll(~okm));   // leading run of usable meshlets (okm has no bit past lane 31)
+  layout = pack_layout(d.x - p.c0, d.y - p.ra, d.z - p.o0, nch);
+  if (p.k) {
+    p.nch = lane_value(ex, p.k - 1) - p.c0;
+    p.nrb = (lane_value(ey, p.k - 1) - p.ra + 15) >> 4;
+    p.tris = lane_value(ez, p.k - 1) - p.o0;
+  } else {
+    p.nch = p.nrb = p.tris = 0;
+  }
+  return p;
+}
+
+__device__ __forceinline__ uint4 load_bits(const Stream& s, const Plan& p, uint32_t lane) {
+  return load16(buffer(s.bits + 16ull * p.c0, 16 * p.nch), 16 * lane);
+}
+
+// The reuse allocation extends to a multiple of 16 bytes, so whole blocks can
+// be read up to the block holding the run's last reuse byte.
+__device__ __forceinline__ uint4 load_reuse(const Stream& s, const Plan& p, uint32_t lane) {
+  return load16(buffer(s.reuse + p.ra, 16 * p.nrb), 16 * lane);
+}
+
+// Decodes the run's meshlets from the tile.
+__device__ __forceinline__ void decode_run(RunTile& tile, const LanePtrs& lp, const Plan& p, uint32_t layout,
+                                           const uint4& bv, uint32_t shift, uint32_t lane) {
+  for (uint32_t i = 0; i < p.k; ++i) {
+    const uint32_t w = lane_value(layout, i);
+    const uint32_t co = w & 63u, ro = (w >> 6) & 2047u, ob = shift + 3 * ((w >> 17) & 4095u);
+    const uint32_t nch = (w >> 29) + 1;
+    if (nch > 2) {
+      if (nch > 3) decode_meshlet<4>(tile, lp, bv, co, ro, ob, lane);
+      else decode_meshlet<3>(tile, lp, bv, co, ro, ob, lane);
     } else {
-      uint8_t* gb = reinterpret_cast<uint8_t*>(g + j);
-      for (uint32_t b = 0; b < 4; ++b)
-        if (lo + b >= shift && lo + b < end) gb[b] = uint8_t(w >> (8 * b));
+      if (nch > 1) decode_meshlet<2>(tile, lp, bv, co, ro, ob, lane);
+      else decode_meshlet<1>(tile, lp, bv, co, ro, ob, lane);
     }
   }
 }
 
-// Decodes meshlets [m, m_end) of stream s with the calling wavefront, run by
-// run.  tile.idx[0..2] must hold 0,1,2.
-__device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32_t m_end, RunTile& tile,
+// Writes the run's tile bytes [shift, shift + 3 * tris) to dst .. dst + 3 *
+// tris (shift = dst mod 16): the 16-byte blocks inside the span with four
+// stores per lane, then the ragged bytes at the two ends (at most 15 each)
+// with one byte store per lane.
+__device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t tris, const RunTile& tile,
                                           uint32_t lane) {
-  while (m < m_end) {
-    const uint32_t cnt = min(m_end - m, kRunMeshlets);
-    uint4 d = make_uint4(0, 0, 0, 0);
-    if (lane < cnt) d = *reinterpret_cast<const uint4*>(s.meshlets + m + lane);
-    const uint32_t T = d.w & 0xFFFFu, V = d.w >> 16;
-    const uint32_t nch = (T + 63) >> 6;
-    const uint32_t nru = T + 2 - V;
-    const uint32_t c0 = uniform(d.x), r0 = uniform(d.y), o0 = uniform(d.z);
-    const uint32_t ra = r0 & ~3u;   // reuse bytes are staged from a dword boundary
-    bool ok = lane < cnt && T - 1u < kMaxStripTris && V >= 3 && V <= 256 && V <= T + 2;
-    ok = ok && uint64_t(d.x) + nch <= s.chunks && uint64_t(d.y) + nru <= s.reuse_bytes &&
-         uint64_t(d.z) + T <= s.out_tris;
-    ok = ok && d.x - c0 + nch <= RunTile::kChunks && d.y - ra + nru <= kRunTris + 3 &&
-         d.z - o0 + T <= kRunTris && d.x >= c0 && d.y >= r0 && d.z >= o0;
-    const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
-    const uint32_t k = uint32_t(__builtin_ctzll(~okm));   // leading run of usable meshlets
-    if (k == 0) {   // the first meshlet is unusable: skip it
-      ++m;
-      continue;
-    }
-    const uint32_t c_end = __builtin_amdgcn_readlane(d.x + nch, k - 1);
-    const uint32_t r_end = __builtin_amdgcn_readlane(d.y + nru, k - 1);
-    const uint32_t o_end = __builtin_amdgcn_readlane(d.z + T, k - 1);
+  uint8_t* base = dst - shift;                      // 16-byte aligned, tile byte 0
+  const uint32_t end = shift + 3 * tris;
+  const uint32_t full0 = (shift + 15) >> 4;         // first block inside the span
+  const uint32_t full1 = end >> 4;                  // one past the last block inside
+  const __amdgpu_buffer_rsrc_t blocks = buffer(base, 16 * full1);
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint32_t j = full0 + lane + kWave * q;
+    const uint32_t jt = j < kOutBlocks ? j : kOutBlocks - 1;
+    store16(blocks, j < full1 ? 16 * j : kOutOfRange, tile.out[jt]);
+  }
+  const uint32_t head_end = min(16 * full0, end);
+  const uint32_t head = head_end - shift;
+  const uint32_t tail_start = max(16 * full1, head_end);
+  const uint32_t tail = end - tail_start;
+  const uint32_t pos = lane < head ? shift + lane : tail_start + (lane - head);
+  const uint32_t byte = reinterpret_cast<const uint8_t*>(tile.out)[pos < 16 * kOutBlocks ? pos : 0];
+  __builtin_amdgcn_raw_buffer_store_b8(uint8_t(byte), buffer(base, end), int(lane < head + tail ? pos : kOutOfRange),
+                                       0, 0);
+}
 
-    // stage flag chunks and reuse bytes
-    const uint4* gbits = reinterpret_cast<const uint4*>(s.bits) + c0;
-    for (uint32_t j = lane; j < c_end - c0; j += kWave) tile.bits[j] = gbits[j];
-    const uint32_t nrd = (r_end - ra + 3) >> 2;
-    uint32_t* treuse = reinterpret_cast<uint32_t*>(tile.reuse);
-    for (uint32_t j = lane; j < nrd; j += kWave) {
-      const uint64_t gofs = uint64_t(ra) + 4 * j;
-      uint32_t v;
-      if (gofs + 4 <= s.reuse_bytes) {
-        v = *reinterpret_cast<const uint32_t*>(s.reuse + gofs);
-      } else {   // the array ends inside this dword
-        v = 0;
-        for (uint32_t b = 0; b < 4; ++b)
-          if (gofs + b < s.reuse_bytes) v |= uint32_t(s.reuse[gofs + b]) << (8 * b);
-      }
-      treuse[j] = v;
-    }
-    wave_lds_sync();
+// The same five stores store_run issues, all out of range: they write
+// nothing.  Issued after the prologue's loads so that both ways into the run
+// loop have five stores after the prefetched loads, which lets the compiler
+// wait for those loads alone.
+__device__ __forceinline__ void store_nothing(uint8_t* any) {
+  const __amdgpu_buffer_rsrc_t none = buffer(any, 0);
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) store16(none, kOutOfRange + 16 * q, make_uint4(q, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), none, int(kOutOfRange), 0, 0);
+}
 
-    uint8_t* dst = s.out + 3ull * o0;
-    const uint32_t shift = uint32_t(reinterpret_cast<uintptr_t>(dst)) & 3u;
-    for (uint32_t i = 0; i < k; ++i) {
-      const uint32_t co = __builtin_amdgcn_readlane(d.x, i) - c0;
-      const uint32_t ro = __builtin_amdgcn_readlane(d.y, i) - ra;
-      const uint32_t oo = __builtin_amdgcn_readlane(d.z, i) - o0;
-      const uint32_t Ti = __builtin_amdgcn_readlane(T, i);
-      decode_meshlet(tile, co, ro, shift + 3 * oo, Ti, lane);
-    }
-    store_span(dst, 3 * (o_end - o0), tile, lane);
+// Decodes meshlets [m, m_end) of stream s with the calling wavefront.
+__device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32_t m_end, RunTile& tile,
+                                             const LanePtrs& lp, uint32_t lane) {
+  if (m >= m_end) return;
+  uint4 d = load_descriptors(s, m, m_end, lane);
+  uint32_t layout;
+  Plan p = make_plan(s, d, m, m_end, lane, layout);
+  uint32_t mn = m + (p.k ? p.k : 1);
+  uint4 dn = load_descriptors(s, mn, m_end, lane);
+  uint4 bv = load_bits(s, p, lane);
+  uint4 rv = load_reuse(s, p, lane);
+  store_nothing(s.out);
+  for (;;) {
+    // the tile is free: stage this run's reuse bytes
+    reinterpret_cast<uint4*>(tile.reuse)[lane] = rv;
+    // plan the next run and start its loads; they overlap this run's decode
+    uint32_t layout_n;
+    const Plan pn = make_plan(s, dn, mn, m_end, lane, layout_n);
+    const uint32_t mnn = mn + (pn.k ? pn.k : 1);
+    const uint4 dnn = load_descriptors(s, mnn, m_end, lane);
+    const uint4 bvn = load_bits(s, pn, lane);
+    const uint4 rvn = load_reuse(s, pn, lane);
     wave_lds_sync();
-    m += k;
+    uint8_t* dst = s.out + 3ull * p.o0;
+    const uint32_t shift = uint32_t(reinterpret_cast<uintptr_t>(dst)) & 15u;
+    decode_run(tile, lp, p, layout, bv, shift, lane);
+    store_run(dst, shift, p.tris, tile, lane);
+    wave_lds_sync();
+    if (mn >= m_end) break;
+    p = pn;
+    layout = layout_n;
+    dn = dnn;
+    bv = bvn;
+    rv = rvn;
+    mn = mnn;
   }
 }
 
-__device__ __forceinline__ RunTile& wave_tile(uint32_t wave, uint32_t lane) {
+__device__ __forceinline__ RunTile& wave_tile(uint32_t wave, uint32_t lane, LanePtrs& lp) {
   extern __shared__ uint4 lds_tiles[];
   RunTile& tile = reinterpret_cast<RunTile*>(lds_tiles)[wave];
   if (lane < 3) tile.idx[lane] = uint8_t(lane);
+  lp.reuse = tile.reuse + lane;
+  lp.idx = tile.idx + lane;
+  lp.out = reinterpret_cast<uint8_t*>(tile.out) + 3 * lane;
   return tile;
 }
 
-// Plain decoder: workgroup b covers waves_per_group * mpw consecutive
-// meshlets; wave w of it the w-th run of mpw.  Consecutive workgroups go to
-// different XCDs, so tiles are handed out XCD-major: each XCD decodes one
-// contiguous stretch of the mesh and its L2 sees whole output lines.
+// Splits [0, n) into one contiguous block per wavefront of the grid, XCD-major:
+// workgroups are dispatched round-robin over the 8 XCDs, so the blocks of one
+// XCD's waves are adjacent and its L2 sees whole output lines.
+__device__ __forceinline__ void wave_block(uint64_t n, uint32_t wave, uint32_t waves, uint64_t& b0, uint64_t& b1) {
+  const uint32_t xcd = blockIdx.x % kXcds;
+  const uint32_t per_xcd = gridDim.x / kXcds;             // the grid is a multiple of 8
+  const uint64_t wx = uint64_t(per_xcd) * waves;          // waves of this XCD
+  const uint64_t q = uint64_t(blockIdx.x / kXcds) * waves + wave;
+  const uint64_t x0 = n * xcd / kXcds, x1 = n * (xcd + 1) / kXcds;
+  b0 = x0 + (x1 - x0) * q / wx;
+  b1 = x0 + (x1 - x0) * (q + 1) / wx;
+}
+
+// Plain decoder: every wavefront decodes one contiguous block of meshlets.
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
     const gtsr_meshlet* __restrict__ meshlets, const uint8_t* __restrict__ bits,
     const uint8_t* __restrict__ reuse, uint8_t* __restrict__ out, uint32_t meshlet_count,
-    uint64_t chunks, uint64_t reuse_bytes, uint64_t out_tris, uint32_t mpw) {
+    uint64_t chunks, uint64_t reuse_bytes, uint64_t out_tris) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = uniform(threadIdx.x / kWave);
-  const uint32_t waves = blockDim.x / kWave;
-  RunTile& tile = wave_tile(wave, lane);
-  const uint32_t per_xcd = gridDim.x / kXcds;
-  const uint32_t group = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-  const uint64_t m0 = (uint64_t(group) * waves + wave) * mpw;
-  if (m0 >= meshlet_count) return;
-  const uint32_t m1 = uint32_t(min(m0 + mpw, uint64_t(meshlet_count)));
-  const Stream s{meshlets, bits, reuse, out, chunks, reuse_bytes, out_tris};
-  decode_range(s, uint32_t(m0), m1, tile, lane);
+  LanePtrs lp;
+  RunTile& tile = wave_tile(wave, lane, lp);
+  uint64_t b0, b1;
+  wave_block(meshlet_count, wave, blockDim.x / kWave, b0, b1);
+  if (b0 >= b1) return;
+  const Stream s{reinterpret_cast<const uint8_t*>(meshlets), bits, reuse, out,
+                 clip32(chunks), clip32(reuse_bytes), clip32(out_tris)};
+  decode_range(s, uint32_t(b0), uint32_t(b1), tile, lp, lane);
 }
 
-// Persistent batched decoder: every wavefront takes work items (a run of
-// meshlets of one mesh) from a shared counter until none are left.
+// Persistent batched decoder: every wavefront takes one contiguous block of
+// the work list (items are balanced by strip triangles) and decodes it as
+// meshlet ranges, merging consecutive items that continue the same mesh.
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
     const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
-    const gtsr_work_item* __restrict__ work, uint32_t work_items, uint32_t* __restrict__ counter) {
+    const gtsr_work_item* __restrict__ work, uint32_t work_items) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = uniform(threadIdx.x / kWave);
-  RunTile& tile = wave_tile(wave, lane);
-  for (;;) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(counter, 1u);
-    item = uniform(item);
-    if (item >= work_items) break;
-    const gtsr_work_item wi = work[item];
-    const uint32_t mesh = uniform(wi.mesh);
-    if (mesh >= mesh_count) continue;
-    const gtsr_mesh_entry& e = table[mesh];
-    Stream s;
-    s.meshlets = e.meshlets;
-    s.bits = e.bits;
-    s.reuse = e.reuse;
-    s.out = e.out;
-    s.chunks = e.bits_bytes / 16;
-    s.reuse_bytes = e.reuse_bytes;
-    s.out_tris = e.strip_triangles;
-    const uint32_t mcount = e.meshlet_count;
-    const uint32_t first = uniform(wi.first);
-    const uint32_t end = min(uniform(wi.end), mcount);
-    if (first < end) decode_range(s, first, end, tile, lane);
+  LanePtrs lp;
+  RunTile& tile = wave_tile(wave, lane, lp);
+  uint64_t b0, b1;
+  wave_block(work_items, wave, blockDim.x / kWave, b0, b1);
+  for (uint64_t base = b0; base < b1; base += kWave) {
+    const uint32_t cnt = uint32_t(min(b1 - base, uint64_t(kWave)));
+    uint4 wi = make_uint4(0xFFFFFFFFu, 0, 0, 0);
+    if (lane < cnt) wi = *reinterpret_cast<const uint4*>(work + base + lane);
+    const uint32_t prev_mesh = __shfl_up(wi.x, 1);
+    const uint32_t prev_end = __shfl_up(wi.z, 1);
+    // lane continues the item before it: same mesh, starts where it ended
+    const uint64_t cont = __builtin_amdgcn_ballot_w64(lane > 0 && lane < cnt && wi.x == prev_mesh &&
+                                                      wi.y == prev_end);
+    uint32_t p = 0;
+    while (p < cnt) {
+      const uint64_t rest = p + 1 < 64 ? (cont >> (p + 1)) : 0ull;
+      const uint32_t more = uint32_t(__builtin_ctzll(~rest));   // items continuing this one
+      const uint32_t last = p + more;
+      const uint32_t mesh = lane_value(wi.x, p);
+      const uint32_t first = lane_value(wi.y, p);
+      const uint32_t end = lane_value(wi.z, last);
+      p = last + 1;
+      if (mesh >= mesh_count) continue;
+      const gtsr_mesh_entry& e = table[mesh];
+      if ((reinterpret_cast<uintptr_t>(e.meshlets) | reinterpret_cast<uintptr_t>(e.bits) |
+           reinterpret_cast<uintptr_t>(e.reuse)) & 15)
+        continue;   // misaligned arrays: the entry is skipped
+      const Stream s{reinterpret_cast<const uint8_t*>(e.meshlets), e.bits, e.reuse, e.out,
+                     clip32(e.bits_bytes / 16), clip32(e.reuse_bytes), clip32(e.strip_triangles)};
+      const uint32_t stop = min(end, e.meshlet_count);
+      if (first < stop) decode_range(s, first, stop, tile, lp, lane);
+    }
   }
 }
 
-__global__ void k_fill_zero(uint32_t* p, uint32_t n) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
-
 struct Defaults {
-  uint32_t waves = 4, mpw = 16, gpc = 8;
+  uint32_t waves = 4, mpw = 8, gpc = 8;
 };
 
 int resolve_cfg(const gtsr_launch_cfg* cfg, Defaults& d, const char* who) {
@@ -306,7 +474,7 @@ int resolve_cfg(const gtsr_launch_cfg* cfg, Defaults& d, const char* who) {
     d.waves = cfg->waves_per_group;
   }
   if (cfg->meshlets_per_wave) {
-    if (cfg->meshlets_per_wave > 64) return fail(GTSR_EINVAL, std::string(who) + ": meshlets_per_wave > 64");
+    if (cfg->meshlets_per_wave > 1024) return fail(GTSR_EINVAL, std::string(who) + ": meshlets_per_wave > 1024");
     d.mpw = cfg->meshlets_per_wave;
   }
   if (cfg->groups_per_cu) {
@@ -338,36 +506,25 @@ int check_launch(const char* who) {
   return ok();
 }
 
+inline uint32_t round_up8(uint64_t g) { return uint32_t((g + kXcds - 1) / kXcds * kXcds); }
+
 int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gtsr_work_item* work,
-                    uint32_t work_items, void* workspace, uint64_t workspace_bytes,
-                    const gtsr_launch_cfg* cfg, hipStream_t stream, const char* who) {
-  if ((mesh_count && !table) || (work_items && !work) || !workspace)
-    return fail(GTSR_EINVAL, std::string(who) + ": null pointer");
-  if (workspace_bytes < kWorkspaceBytes || (reinterpret_cast<uintptr_t>(workspace) & 255))
-    return fail(GTSR_EINVAL, std::string(who) + ": workspace must be >= 256 bytes, 256-byte aligned");
+                    uint32_t work_items, const gtsr_launch_cfg* cfg, hipStream_t stream, const char* who) {
+  if ((mesh_count && !table) || (work_items && !work)) return fail(GTSR_EINVAL, std::string(who) + ": null pointer");
   if ((reinterpret_cast<uintptr_t>(table) & 15) || (reinterpret_cast<uintptr_t>(work) & 15))
     return fail(GTSR_EINVAL, std::string(who) + ": tables must be 16-byte aligned");
   Defaults d;
+  d.waves = 2;    // measured best for the persistent grid: 2-wave groups, 16 per CU
+  d.gpc = 16;
   if (int rc = resolve_cfg(cfg, d, who)) return rc;
   const uint32_t cus = cu_count();
   if (!cus) return fail(GTSR_EHIP, std::string(who) + ": cannot query the device");
-  uint32_t* counter = static_cast<uint32_t*>(workspace);
-  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, stream, counter, uint32_t(kWorkspaceBytes / 4));
-  if (int rc = check_launch(who)) return rc;
-  uint32_t groups = cus * d.gpc;
-  groups = (groups + kXcds - 1) / kXcds * kXcds;
+  if (work_items == 0) return ok();
+  const uint32_t groups = round_up8(uint64_t(cus) * d.gpc);
   hipLaunchKernelGGL(k_decode_batched, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes, stream,
-                     table, mesh_count, work, work_items, counter);
+                     table, mesh_count, work, work_items);
   return check_launch(who);
 }
-
-}  // namespace
-}  // namespace gtsr
-
-using namespace gtsr;
-
-namespace gtsr {
-namespace {
 
 int check_plain_args(const gtsr_stream* dev, const uint8_t* dev_out, uint64_t out_bytes) {
   if (!dev) return fail(GTSR_EINVAL, "decode_meshlets: null stream");
@@ -376,33 +533,39 @@ int check_plain_args(const gtsr_stream* dev, const uint8_t* dev_out, uint64_t ou
     return fail(GTSR_EINVAL, "decode_meshlets: null device pointer");
   if (out_bytes / 3 < dev->strip_triangles)
     return fail(GTSR_EINVAL, "decode_meshlets: out_bytes < 3 * strip_triangles");
-  if ((reinterpret_cast<uintptr_t>(dev->meshlets) & 15) || (reinterpret_cast<uintptr_t>(dev->bits) & 15))
-    return fail(GTSR_EINVAL, "decode_meshlets: meshlets and bits must be 16-byte aligned");
-  const uint64_t groups = (uint64_t(dev->meshlet_count) + 15) / 16 * 16;
-  if (groups > 0x7FFFFFFFull) return fail(GTSR_ELIMIT, "decode_meshlets: grid too large");
+  if ((reinterpret_cast<uintptr_t>(dev->meshlets) | reinterpret_cast<uintptr_t>(dev->bits) |
+       reinterpret_cast<uintptr_t>(dev->reuse)) & 15)
+    return fail(GTSR_EINVAL, "decode_meshlets: meshlets, bits and reuse must be 16-byte aligned");
   return GTSR_OK;
 }
 
-void launch_plain(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, const Defaults& d,
-                  hipStream_t stream) {
-  if (dev->meshlet_count == 0) return;
-  const uint64_t per_group = uint64_t(d.waves) * d.mpw;
-  uint64_t groups = (dev->meshlet_count + per_group - 1) / per_group;
-  groups = (groups + kXcds - 1) / kXcds * kXcds;
-  hipLaunchKernelGGL(k_decode_plain, dim3(uint32_t(groups)), dim3(kWave * d.waves), d.waves * kTileBytes,
-                     stream, dev->meshlets, dev->bits, dev->reuse, dev_out, dev->meshlet_count,
-                     dev->bits_bytes / 16, dev->reuse_bytes, out_bytes / 3, d.mpw);
+// Grid: one wave per mpw meshlets, capped at groups_per_cu resident groups
+// per CU (each wave then takes a larger contiguous block).
+int launch_plain(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, const Defaults& d,
+                 uint32_t cus, hipStream_t stream) {
+  if (dev->meshlet_count == 0) return GTSR_OK;
+  const uint64_t waves = (uint64_t(dev->meshlet_count) + d.mpw - 1) / d.mpw;
+  uint64_t groups = (waves + d.waves - 1) / d.waves;
+  groups = std::min<uint64_t>(groups, uint64_t(cus) * d.gpc);
+  hipLaunchKernelGGL(k_decode_plain, dim3(round_up8(groups)), dim3(kWave * d.waves), d.waves * kTileBytes, stream,
+                     dev->meshlets, dev->bits, dev->reuse, dev_out, dev->meshlet_count, dev->bits_bytes / 16,
+                     dev->reuse_bytes, out_bytes / 3);
+  return GTSR_OK;
 }
 
 }  // namespace
 }  // namespace gtsr
+
+using namespace gtsr;
 
 extern "C" int gtsr_decode_meshlets_cfg(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes,
                                         const gtsr_launch_cfg* cfg, void* hip_stream) {
   if (int rc = check_plain_args(dev, dev_out, out_bytes)) return rc;
   Defaults d;
   if (int rc = resolve_cfg(cfg, d, "decode_meshlets")) return rc;
-  launch_plain(dev, dev_out, out_bytes, d, static_cast<hipStream_t>(hip_stream));
+  const uint32_t cus = cu_count();
+  if (!cus) return fail(GTSR_EHIP, "decode_meshlets: cannot query the device");
+  launch_plain(dev, dev_out, out_bytes, d, cus, static_cast<hipStream_t>(hip_stream));
   return check_launch("decode_meshlets");
 }
 
@@ -415,8 +578,10 @@ extern "C" int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* co
   if (int rc = resolve_cfg(cfg, d, "gtsr_decode_meshlets_many")) return rc;
   for (uint32_t i = 0; i < n; ++i)
     if (int rc = check_plain_args(&streams[i], dev_outs[i], out_bytes[i])) return rc;
+  const uint32_t cus = cu_count();
+  if (!cus) return fail(GTSR_EHIP, "gtsr_decode_meshlets_many: cannot query the device");
   for (uint32_t i = 0; i < n; ++i)
-    launch_plain(&streams[i], dev_outs[i], out_bytes[i], d, static_cast<hipStream_t>(hip_stream));
+    launch_plain(&streams[i], dev_outs[i], out_bytes[i], d, cus, static_cast<hipStream_t>(hip_stream));
   return check_launch("gtsr_decode_meshlets_many");
 }
 
@@ -424,19 +589,15 @@ extern "C" int decode_meshlets(const gtsr_stream* dev, uint8_t* dev_out, uint64_
   return gtsr_decode_meshlets_cfg(dev, dev_out, out_bytes, nullptr, hip_stream);
 }
 
-extern "C" uint64_t gtsr_batched_workspace_bytes(void) { return kWorkspaceBytes; }
-
 extern "C" int decode_meshlets_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
                                        const gtsr_work_item* dev_work, uint32_t work_items,
-                                       void* dev_workspace, uint64_t workspace_bytes,
                                        const gtsr_launch_cfg* cfg, void* hip_stream) {
-  return enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, dev_workspace, workspace_bytes,
-                         cfg, static_cast<hipStream_t>(hip_stream), "decode_meshlets_batched");
+  return enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, cfg,
+                         static_cast<hipStream_t>(hip_stream), "decode_meshlets_batched");
 }
 
 extern "C" int gtsr_batched_graph_create(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
                                          const gtsr_work_item* dev_work, uint32_t work_items,
-                                         void* dev_workspace, uint64_t workspace_bytes,
                                          const gtsr_launch_cfg* cfg, void** graph_exec) {
   const char* who = "gtsr_batched_graph_create";
   if (!graph_exec) return fail(GTSR_EINVAL, "gtsr_batched_graph_create: null graph_exec");
@@ -449,13 +610,12 @@ extern "C" int gtsr_batched_graph_create(const gtsr_mesh_entry* dev_mesh_table, 
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     rc = fail(GTSR_EHIP, "gtsr_batched_graph_create: begin capture failed");
   } else {
-    rc = enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, dev_workspace, workspace_bytes,
-                         cfg, s, who);
+    rc = enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, cfg, s, who);
     hipError_t e = hipStreamEndCapture(s, &graph);
     if (rc == GTSR_OK && e != hipSuccess)
       rc = fail(GTSR_EHIP, std::string(who) + ": end capture: " + hipGetErrorString(e));
   }
-  if (rc == GTSR_OK) {
+  if (rc == GTSR_OK && graph) {
     hipGraphExec_t exec = nullptr;
     hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) rc = fail(GTSR_EHIP, std::string(who) + ": instantiate: " + hipGetErrorString(e));

@@ -35,9 +35,7 @@ def say(*a):
 
 
 def device_stream(desc, bits, reuse, ts):
-    dev = "cuda"
-    up = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.uint8)).to(dev) if a.size else \
-        torch.zeros(16, dtype=torch.uint8, device=dev)[:0]
+    up = lambda a: P.upload_padded(np.ascontiguousarray(a, np.uint8), "cuda")
     return P.DeviceStream(up(desc), up(bits), up(reuse), desc.size // 16, ts)
 
 
@@ -79,6 +77,25 @@ def test_random_long_streams():
         ms.append(([1] * T, [0] + [1] * min(T - 1, 253) + [0] * max(0, T - 1 - 253), [1] * max(0, T - 1 - 253)))
     desc, bits, reuse, ts = pack(ms)
     assert_parity(desc, bits, reuse, ts, CFGS, "random long")
+
+
+def test_flag_word_bit31_regression():
+    """Flag words with bit 31 set and bits 32..63 clear (and the mirror case):
+    a sign-extended low half would corrupt the high half of the word."""
+    ms = []
+    for T in (33, 40, 64, 65, 100, 128, 200, 256):
+        for pos in (31, 30, 63):
+            f = [1 if t % 64 == pos else 0 for t in range(T)]
+            g = [0] + [1] * min(T - 1, 253) + [0] * max(0, T - 1 - 253)
+            r = [1] * max(0, T - 1 - 253)
+            ms.append((f, g, r))
+            inc_hole = [0] + [0 if t % 64 == pos else 1 for t in range(1, T)]
+            n_new = sum(inc_hole)
+            if n_new > 253:
+                continue
+            ms.append((f, inc_hole, [0] * (T - 1 - n_new)))
+    desc, bits, reuse, ts = pack(ms)
+    assert_parity(desc, bits, reuse, ts, CFGS[:2], "bit31")
 
 
 MESHES = {
