@@ -92,6 +92,98 @@ def build_sphere():
     return [P.encode(m.tri, m.nverts, 64, 126, threads=0)]
 
 
+def build_serve_prototypes(threads: int):
+    """The serving pool's 96 distinct encoded meshes (kind x caps x log-size level)."""
+    import meshgen
+    import paper_2404_06359_amd as P
+
+    keys = [(k, c, l) for k in range(2) for c in range(3) for l in range(meshgen.SERVE_LEVELS)]
+
+    def one(key):
+        m = meshgen.workload5_prototype(*key)
+        return P.encode(m.tri, m.nverts, m.max_vertices, m.max_triangles, threads=1)
+
+    # largest first so the long encodes start early
+    order = sorted(range(len(keys)), key=lambda i: -keys[i][2])
+    protos = [None] * len(keys)
+    with ThreadPoolExecutor(threads) as ex:
+        for i, e in zip(order, ex.map(lambda i: one(keys[i]), order)):
+            protos[i] = e
+    return protos
+
+
+def run_serve(args, threads):
+    """Open-loop serving run: a Poisson stream of decode requests over a
+    device-resident pool, admitted by an HBM budget, batched continuously."""
+    import torch
+    import meshgen
+    import paper_2404_06359_amd as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    protos = build_serve_prototypes(threads)
+    entries = meshgen.workload5_entries(args.pool_meshes)
+    encs = [protos[int(k)] for k in entries]
+    pool = P.Pool(encs, device=dev, out=False)
+    prep_s = time.perf_counter() - t0
+    pool_bytes = int(pool.d_meshlets.numel() + pool.d_bits.numel() + pool.d_reuse.numel())
+    in_tris = np.array([e.stats["input_triangles"] for e in encs], np.float64)
+    log(f"[bench] serve prep {prep_s:.1f}s: {len(encs)} pool meshes from {len(protos)} prototypes, "
+        f"{in_tris.sum() / 1e9:.2f} G triangles, pool {pool_bytes / 1e9:.2f} GB on the device")
+    budget = int(args.hbm_budget_gb * 1e9)
+    arena = budget - pool_bytes
+    assert arena > 0, "HBM budget smaller than the pool"
+    srv = P.Server(pool, arena_bytes=arena, max_inflight=args.max_inflight, max_batch=args.max_batch,
+                   target_tris=args.target_tris)
+    rng = meshgen.rng_for(5, 999999)
+    warm = int(round(args.rate * args.warm_s))
+    n = warm + args.requests
+    gaps = rng.exponential(1e9 / args.rate, n)
+    arrivals = np.cumsum(gaps).astype(np.uint64)
+    meshes = rng.integers(0, len(encs), n).astype(np.uint32)
+    log(f"[bench] serve: {n} requests ({warm} warm-up) at {args.rate:.0f}/s, budget {budget / 1e9:.0f} GB "
+        f"(arena {arena / 1e9:.1f} GB)")
+    comp, start = srv.replay(arrivals, meshes)
+    stats = srv.stats()
+    srv.close()
+    c = comp[warm:]
+    lat = (c["t_done_ns"] - c["t_submit_ns"]) / 1e3
+    queue = (c["t_admit_ns"] - c["t_submit_ns"]) / 1e3
+    late = (c["t_submit_ns"] - (start + arrivals[warm:])) / 1e3
+    span = (int(c["t_done_ns"].max()) - int(start + arrivals[warm])) / 1e9
+    tris = in_tris[c["mesh"]].sum()
+    pct = lambda a: {"p50": round(float(np.percentile(a, 50)), 1), "p99": round(float(np.percentile(a, 99)), 1),
+                     "p99.9": round(float(np.percentile(a, 99.9)), 1), "mean": round(float(a.mean()), 1),
+                     "max": round(float(a.max()), 1)}
+    return {
+        "metric": "serving: p50/p99 decode-request latency + decoded triangles/s",
+        "value": tris / span / 1e9,
+        "unit": "Gtps",
+        "n_gpus": 1,
+        "steps": int(args.requests),
+        "warmup": warm,
+        "ms_per_step": span * 1e3 / args.requests,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"serving: Poisson {args.rate:.0f} req/s over a device-resident pool of "
+                               f"{len(encs)} meshes (1e4-2e7 triangles log-uniform, {len(protos)} encoded "
+                               f"prototypes), {args.hbm_budget_gb:.0f} GB HBM budget, continuous batching",
+                   "pool_meshes": len(encs), "pool_triangles": int(in_tris.sum()), "pool_bytes": pool_bytes,
+                   "arena_bytes": arena, "max_inflight": args.max_inflight, "max_batch": args.max_batch,
+                   "target_tris": args.target_tris, "prep_seconds": round(prep_s, 1)},
+        "latency_us": pct(lat),
+        "queue_us": pct(queue),
+        "submit_lateness_us": pct(late),
+        "offered_Gtps": float(in_tris[c["mesh"]].sum() / ((int(arrivals[-1]) - int(arrivals[warm])) / 1e9) / 1e9),
+        "requests_per_s": args.requests / span,
+        "server": stats,
+    }
+
+
 def algorithmic_bytes(encs) -> int:
     """Per launch: every descriptor (16 B), flag chunk (16 B per 64 strip
     triangles) and reuse byte read once; 3 output bytes per strip triangle
@@ -142,12 +234,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["batched", "sphere"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "sphere", "serve"], default="batched")
+    ap.add_argument("--pool-meshes", type=int, default=5000, help="serve: pool size")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: mean requests per second")
+    ap.add_argument("--requests", type=int, default=20000, help="serve: measured requests")
+    ap.add_argument("--warm-s", type=float, default=1.0, help="serve: warm-up seconds of arrivals")
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: pool + outputs budget")
+    ap.add_argument("--max-inflight", type=int, default=4, help="serve: batches on the device at once")
+    ap.add_argument("--max-batch", type=int, default=256, help="serve: requests per batch")
     ap.add_argument("--meshes", type=int, default=2000)
     ap.add_argument("--target-tris", type=int, default=768)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--groups-per-cu", type=int, default=0)
     ap.add_argument("--meshlets-per-wave", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: use --target-tris and the launch flags as given instead of measuring")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-mesh", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -166,6 +267,9 @@ def main():
     import paper_2404_06359_amd as P
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args, host_threads())))
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     threads = host_threads()
@@ -184,14 +288,23 @@ def main():
     pool = P.Pool(encs, device=dev)
     cfg = {"waves_per_group": args.waves, "groups_per_cu": args.groups_per_cu,
            "meshlets_per_wave": args.meshlets_per_wave}
+    plain_cfg = dict(cfg)
     stream = torch.cuda.current_stream()
+    tuned = None
     if args.workload == "batched":
         pool.plan(args.target_tris)
+        if not args.no_autotune:
+            t0 = time.perf_counter()
+            cfg, best, points = pool.autotune(stream=stream)
+            tuned = {"target_tris": best["target_tris"], "waves_per_group": best["waves_per_group"],
+                     "groups_per_cu": best["groups_per_cu"], "points": len(points),
+                     "seconds": round(time.perf_counter() - t0, 2)}
+            log(f"[bench] autotune: {len(points)} shapes, best {best}")
         graph = pool.batched_graph(cfg)
         step = lambda: graph(stream)
         kernel = "decode_batched"
     else:
-        step = lambda: pool.decode_per_mesh(stream, cfg)
+        step = lambda: pool.decode_per_mesh(stream, plain_cfg)
         kernel = "decode_plain"
 
     for _ in range(args.warmup):
@@ -210,12 +323,12 @@ def main():
     per_mesh = None
     if args.workload == "batched" and not args.no_per_mesh:
         for _ in range(2):
-            pool.decode_per_mesh(stream, cfg)
+            pool.decode_per_mesh(stream, plain_cfg)
         torch.cuda.synchronize()
         pm_steps = max(3, args.steps // 4)
         ev0.record(stream)
         for _ in range(pm_steps):
-            pool.decode_per_mesh(stream, cfg)
+            pool.decode_per_mesh(stream, plain_cfg)
         ev1.record(stream)
         torch.cuda.synchronize()
         pm_ms = ev0.elapsed_time(ev1) / pm_steps
@@ -267,6 +380,7 @@ def main():
         "config": {"workload": workload, "meshes": len(encs), "input_triangles": in_tris,
                    "strip_triangles": strip_tris, "meshlets": meshlets, "restarts": restarts,
                    "work_items": pool.work_items, "launch": {k: v for k, v in cfg.items() if v},
+                   "autotuned": tuned,
                    "prep_seconds": round(prep_s, 2)},
         "roofline": roof,
         "per_mesh": per_mesh,

@@ -207,7 +207,8 @@ int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_ou
  * meshlets, bits and reuse pointer (entries that are not are skipped); each
  * reuse allocation must extend to a multiple of 16 bytes (as for
  * decode_meshlets).  The grid is sized to stay resident (groups_per_cu groups on
- * every CU); each wavefront decodes one contiguous block of the work list,
+ * every CU, fewer when the list has fewer items than that grid has
+ * wavefronts); each wavefront decodes one contiguous block of the work list,
  * so the list should be balanced by strip triangles (gtsr_plan_batch) and
  * have many more items than the grid has wavefronts.  No atomics, no
  * scratch memory.  Same skipping rule as decode_meshlets; items naming a
@@ -223,6 +224,121 @@ int decode_meshlets_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh
 int gtsr_batched_graph_create(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
                               const gtsr_work_item* dev_work, uint32_t work_items,
                               const gtsr_launch_cfg* cfg, void** graph_exec);
+
+/* One measured launch shape of gtsr_autotune_batched (32 bytes). */
+typedef struct gtsr_tune_point {
+  uint32_t target_tris;       /* gtsr_plan_batch target the work list was built with */
+  uint32_t work_items;        /* items in that work list */
+  gtsr_launch_cfg cfg;        /* waves_per_group, groups_per_cu (meshlets_per_wave unused) */
+  float median_ms, min_ms;    /* over the timed launches */
+} gtsr_tune_point;
+
+/* Pick the batched decoder's launch shape by measurement (the paper decodes
+ * one meshlet per workgroup and has no such knob).
+ * For every target in targets[n_targets] (strip triangles per work item,
+ * i.e. meshlets per wavefront step; NULL or 0 = 384, 768, 1536, 3072) the
+ * work list is planned as gtsr_plan_batch does, and for every shape in
+ * cfgs[n_cfgs] (NULL or 0 = six waves-per-group x groups-per-CU pairs of 32
+ * resident wavefronts per CU) one warm-up and reps timed launches
+ * (0 = 5, at most 1000) of decode_meshlets_batched run on hip_stream, each
+ * timed with HIP events.  *best receives the point with the lowest median;
+ * points (may be NULL) receives up to capacity points in measurement order
+ * and *point_count (may be NULL) the number measured.  host_meshlets and
+ * meshlet_counts describe the same meshes as dev_mesh_table (as for
+ * gtsr_plan_batch).  Synchronous: returns after the last timed launch.  It
+ * allocates one device work list for its own use and frees it.  Every launch
+ * decodes the whole table, so the table's outputs hold the decoded meshes on
+ * return.  Errors: EINVAL (null argument, target 0, bad cfg), EHIP. */
+int gtsr_autotune_batched(const gtsr_meshlet* const* host_meshlets, const uint32_t* meshlet_counts,
+                          const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
+                          const uint32_t* targets, uint32_t n_targets, const gtsr_launch_cfg* cfgs,
+                          uint32_t n_cfgs, uint32_t reps, gtsr_tune_point* points, uint32_t capacity,
+                          uint32_t* point_count, gtsr_tune_point* best, void* hip_stream);
+
+/* ------------------------------------------------------------ serving */
+
+/* A decode-request server over a device-resident pool of encoded meshes
+ * (continuous batching; not in the paper, which decodes inside a renderer).
+ * A scheduler thread admits requests first-come first-served while each one's
+ * output (3 * strip_triangles bytes) fits into the output arena and a launch
+ * slot is free; the requests admitted together go to the device as one
+ * decode_meshlets_batched launch on the slot's own HIP stream, so up to
+ * max_inflight batches decode at once and new requests join as slots and
+ * arena space free up.  A request that does not fit blocks those behind it.
+ * Outputs stay in the arena until gtsr_server_release. */
+typedef struct gtsr_server gtsr_server;   /* opaque */
+
+typedef struct gtsr_server_params {
+  uint8_t* arena;            /* device memory for decoded outputs, caller-owned, 256-byte aligned */
+  uint64_t arena_bytes;      /* the admission budget for outputs in flight or unreleased */
+  uint32_t max_inflight;     /* batches on the device at once, 1..8 (0 = 4) */
+  uint32_t max_batch;        /* requests per batch, 1..65536 (0 = 256) */
+  uint32_t target_tris;      /* strip triangles per work item (0 = 768) */
+  uint32_t max_items;        /* work items per batch, 1..2^26 (0 = 2^20); a mesh that
+                                would need more is split into coarser items */
+  gtsr_launch_cfg cfg;       /* launch shape of every batch (zeros = defaults) */
+  uint32_t reserved;         /* must be 0 */
+  uint32_t reserved2;
+} gtsr_server_params;
+
+/* One finished request.  Times are steady-clock nanoseconds: submitted,
+ * admitted (arena space granted, batch formed), seen finished by the
+ * scheduler. */
+typedef struct gtsr_completion {
+  uint64_t tag;              /* the caller's tag from gtsr_server_submit */
+  uint32_t mesh;
+  int32_t status;            /* GTSR_OK, or the error that failed the batch */
+  uint64_t out_offset;       /* the output's byte offset in the arena */
+  uint64_t out_bytes;        /* 3 * strip_triangles of the mesh */
+  uint64_t t_submit_ns, t_admit_ns, t_done_ns;
+} gtsr_completion;
+
+typedef struct gtsr_server_stats {
+  uint64_t submitted, completed, batches, max_batch_seen;
+  uint64_t strip_triangles;  /* decoded by completed requests */
+  uint64_t max_arena_used, arena_used, pending;
+} gtsr_server_stats;
+
+/* host_table: host copy of the pool's mesh table (device stream pointers;
+ * the out field is ignored, outputs go to the arena); host_meshlets[i]: mesh
+ * i's host descriptors (read during this call only, to plan its work items).
+ * The pool's device arrays must outlive the server.  Creates max_inflight HIP
+ * streams (default priority), pinned and device staging of max_batch table
+ * rows and max_items work items per slot, and the scheduler thread, all on
+ * the current device.  Errors: EINVAL, ENOMEM, EHIP. */
+int gtsr_server_create(const gtsr_mesh_entry* host_table, const gtsr_meshlet* const* host_meshlets,
+                       uint32_t mesh_count, const gtsr_server_params* params, gtsr_server** server);
+
+/* Queue a decode of mesh under a caller-chosen tag, unique among the
+ * requests not yet released.  Thread-safe, returns at once.  Errors: EINVAL
+ * (mesh out of range, tag in use), ELIMIT (the output can never fit the
+ * arena). */
+int gtsr_server_submit(gtsr_server* server, uint32_t mesh, uint64_t tag);
+
+/* Move up to capacity finished requests to out (oldest first) and their number
+ * to *count; waits up to timeout_us microseconds for the first one.
+ * Errors: EINVAL, EHIP (the scheduler thread could not start). */
+int gtsr_server_poll(gtsr_server* server, gtsr_completion* out, uint32_t capacity, uint32_t* count,
+                     uint32_t timeout_us);
+
+/* Give a finished request's arena range back to the budget; the output may
+ * be overwritten afterwards.  Errors: EINVAL (unknown tag, still decoding). */
+int gtsr_server_release(gtsr_server* server, uint64_t tag);
+
+int gtsr_server_get_stats(gtsr_server* server, gtsr_server_stats* stats);
+
+/* Client loop for open-loop measurement: submits request i (mesh meshes[i],
+ * tag tag_base + i) at arrival_ns[i] nanoseconds (non-decreasing) after the
+ * call starts (*start_ns receives the start, steady clock; may be NULL),
+ * releases each output as soon as it finishes, and stores request i's
+ * completion in out[i].  Returns when all n have finished.  Errors: those of
+ * submit, poll and release; a failed decode returns its status. */
+int gtsr_server_replay(gtsr_server* server, const uint64_t* arrival_ns, const uint32_t* meshes, uint32_t n,
+                       uint64_t tag_base, gtsr_completion* out, uint64_t* start_ns);
+
+/* Stop the scheduler, wait for batches on the device, free everything the
+ * server allocated (not the arena). */
+void gtsr_server_destroy(gtsr_server* server);
 
 /* Enqueue a captured graph on hip_stream.  Errors: EINVAL, EHIP. */
 int gtsr_graph_launch(void* graph_exec, void* hip_stream);

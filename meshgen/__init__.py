@@ -273,6 +273,48 @@ def workload4_mesh(i: int, lo: float = 5e4, hi: float = 1e6) -> Mesh:
     return m
 
 
+def workload4(count: int = 200, threads: int = 1) -> list:
+    """The stress workload: meshes 0..count-1 of ``workload4_mesh``, generated
+    on ``threads`` threads (Qhull runs outside the interpreter lock)."""
+    if threads <= 1:
+        return [workload4_mesh(i) for i in range(count)]
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(workload4_mesh, range(count)))
+
+
+SERVE_LO, SERVE_HI, SERVE_LEVELS = 1e4, 2e7, 16
+
+
+def workload5_prototype(kind: int, cap: int, level: int) -> Mesh:
+    """Prototype of the serving pool: ``kind`` 0 = grid, 1 = sphere patch; caps
+    ``CAPS[cap]``; triangle count at the centre of log-size level ``level`` of
+    ``SERVE_LEVELS`` equal steps over [1e4, 2e7]."""
+    r = rng_for(5, 100000 + (kind * 3 + cap) * SERVE_LEVELS + level)
+    step = math.log(SERVE_HI / SERVE_LO) / SERVE_LEVELS
+    n = int(round(SERVE_LO * math.exp((level + 0.5) * step)))
+    m = grid_for(n, r) if kind == 0 else sphere_patch(n, r)
+    m.max_vertices, m.max_triangles = CAPS[cap]
+    m.meta["target_n"] = n
+    return m
+
+
+def workload5_entries(count: int = 5000) -> np.ndarray:
+    """Pool entry i -> prototype index ``(kind * 3 + cap) * SERVE_LEVELS + level``:
+    its triangle count is drawn log-uniform in [1e4, 2e7] and rounded to the
+    nearest level, kind and caps uniform."""
+    out = np.zeros(count, np.int64)
+    step = math.log(SERVE_HI / SERVE_LO) / SERVE_LEVELS
+    for i in range(count):
+        r = rng_for(5, i)
+        u = r.uniform(0.0, math.log(SERVE_HI / SERVE_LO))
+        level = min(SERVE_LEVELS - 1, int(u / step))
+        kind, cap = int(r.integers(2)), int(r.integers(3))
+        out[i] = (kind * 3 + cap) * SERVE_LEVELS + level
+    return out
+
+
 def workload5_mesh(i: int, lo: float = 1e4, hi: float = 2e7) -> Mesh:
     """Mesh ``i`` of the serving pool: like the batched workload, triangle
     count log-uniform in [lo, hi]."""

@@ -23,7 +23,9 @@ EXPORTED = (
     "encode_meshlets", "gtsr_encoded_view_get", "gtsr_encoded_free", "gtsr_validate",
     "gtsr_plan_batch", "decode_meshlets", "gtsr_decode_meshlets_cfg", "gtsr_decode_meshlets_many",
     "decode_meshlets_batched", "gtsr_batched_graph_create", "gtsr_graph_launch",
-    "gtsr_graph_destroy", "gtsr_device_cu_count", "gtsr_last_error",
+    "gtsr_graph_destroy", "gtsr_device_cu_count", "gtsr_last_error", "gtsr_autotune_batched",
+    "gtsr_server_create", "gtsr_server_submit", "gtsr_server_poll", "gtsr_server_release",
+    "gtsr_server_get_stats", "gtsr_server_replay", "gtsr_server_destroy",
 )
 
 
@@ -65,6 +67,32 @@ class LaunchCfg(C.Structure):
                 ("groups_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class TunePoint(C.Structure):
+    _fields_ = [("target_tris", C.c_uint32), ("work_items", C.c_uint32), ("cfg", LaunchCfg),
+                ("median_ms", C.c_float), ("min_ms", C.c_float)]
+
+    def as_dict(self) -> dict:
+        return {"target_tris": self.target_tris, "work_items": self.work_items,
+                "waves_per_group": self.cfg.waves_per_group, "groups_per_cu": self.cfg.groups_per_cu,
+                "median_ms": self.median_ms, "min_ms": self.min_ms}
+
+
+class ServerParams(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("max_inflight", C.c_uint32),
+                ("max_batch", C.c_uint32), ("target_tris", C.c_uint32), ("max_items", C.c_uint32),
+                ("cfg", LaunchCfg), ("reserved", C.c_uint32), ("reserved2", C.c_uint32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "batches", "max_batch_seen",
+                                           "strip_triangles", "max_arena_used", "arena_used", "pending")]
+
+
+COMPLETION_DTYPE = np.dtype([("tag", "<u8"), ("mesh", "<u4"), ("status", "<i4"), ("out_offset", "<u8"),
+                             ("out_bytes", "<u8"), ("t_submit_ns", "<u8"), ("t_admit_ns", "<u8"),
+                             ("t_done_ns", "<u8")])
+assert COMPLETION_DTYPE.itemsize == 56
+
 MESH_ENTRY_DTYPE = np.dtype([("meshlets", "<u8"), ("bits", "<u8"), ("reuse", "<u8"), ("out", "<u8"),
                              ("meshlet_count", "<u4"), ("reserved0", "<u4"), ("bits_bytes", "<u8"),
                              ("reuse_bytes", "<u8"), ("strip_triangles", "<u8")])
@@ -101,6 +129,15 @@ def lib():
         "gtsr_graph_destroy": (None, [vp]),
         "gtsr_device_cu_count": (u32, []),
         "gtsr_last_error": (C.c_char_p, []),
+        "gtsr_autotune_batched": (C.c_int, [vp, vp, vp, u32, vp, u32, vp, u32, u32, vp, u32, C.POINTER(u32),
+                                            C.POINTER(TunePoint), vp]),
+        "gtsr_server_create": (C.c_int, [vp, vp, u32, C.POINTER(ServerParams), C.POINTER(vp)]),
+        "gtsr_server_submit": (C.c_int, [vp, u32, u64]),
+        "gtsr_server_poll": (C.c_int, [vp, vp, u32, C.POINTER(u32), u32]),
+        "gtsr_server_release": (C.c_int, [vp, u64]),
+        "gtsr_server_get_stats": (C.c_int, [vp, C.POINTER(ServerStats)]),
+        "gtsr_server_replay": (C.c_int, [vp, vp, vp, u32, u64, vp, C.POINTER(u64)]),
+        "gtsr_server_destroy": (None, [vp]),
     }
     for name, (rt, args) in sig.items():
         f = getattr(L, name)
@@ -439,6 +476,31 @@ class Pool:
             if items.size else torch.zeros(16, dtype=torch.uint8, device=self.table.device)
         return self
 
+    def autotune(self, targets=None, cfgs=None, reps: int = 5, stream=None):
+        """Measure the batched decoder over launch shapes (``gtsr_autotune_batched``),
+        re-plan with the fastest target and return ``(best_cfg, best, points)``:
+        ``best_cfg`` is a dict for ``decode_batched`` / ``batched_graph``,
+        ``best`` and ``points`` are ``TunePoint.as_dict()`` records."""
+        L = lib()
+        n = self.mesh_count
+        arrs = [np.ascontiguousarray(a, MESHLET_DTYPE) for a in self.host_meshlets]
+        ptrs = (C.c_void_p * max(n, 1))(*[a.ctypes.data if a.size else None for a in arrs])
+        tg = np.array(targets or [], np.uint32)
+        cf = (LaunchCfg * max(len(cfgs or []), 1))()
+        for i, c in enumerate(cfgs or []):
+            cf[i] = LaunchCfg(int(c.get("waves_per_group", 0)), 0, int(c.get("groups_per_cu", 0)), 0)
+        cap = max(1, len(tg) or 4) * max(1, len(cfgs or []) or 6)
+        pts = (TunePoint * cap)()
+        cnt = C.c_uint32()
+        best = TunePoint()
+        _check(L.gtsr_autotune_batched(ptrs, self.meshlet_counts.ctypes.data, self.table.data_ptr(), n,
+                                       tg.ctypes.data if tg.size else None, int(tg.size),
+                                       cf if cfgs else None, len(cfgs or []), reps, pts, cap, C.byref(cnt),
+                                       C.byref(best), _stream_handle(stream)))
+        self.plan(int(best.target_tris))
+        cfg = {"waves_per_group": int(best.cfg.waves_per_group), "groups_per_cu": int(best.cfg.groups_per_cu)}
+        return cfg, best.as_dict(), [pts[i].as_dict() for i in range(min(cnt.value, cap))]
+
     def decode_batched(self, stream=None, cfg=None):
         if self.work is None:
             self.plan()
@@ -459,3 +521,76 @@ class Pool:
         """One plain launch per mesh, back to back (enqueued from C)."""
         _check(lib().gtsr_decode_meshlets_many(self.streams, self.out_ptrs, self.out_bytes, self.mesh_count,
                                                _cfg(cfg), _stream_handle(stream)))
+
+
+class Server:
+    """Decode-request server over a ``Pool`` (``gtsr_server_*``): requests are
+    admitted first-come first-served while their output fits the device arena
+    of ``arena_bytes`` (the HBM budget for outputs in flight) and decoded in
+    batches, up to ``max_inflight`` batches on the device at once."""
+
+    def __init__(self, pool: "Pool", arena_bytes: int, max_inflight: int = 4, max_batch: int = 256,
+                 target_tris: int = 768, max_items: int = 0, cfg=None):
+        torch = _torch()
+        self.pool = pool
+        self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=pool.table.device)
+        base = self.arena.data_ptr()
+        self._arena_base = (base + 255) // 256 * 256
+        c = LaunchCfg(0, 0, 0, 0)
+        if cfg:
+            c = LaunchCfg(int(cfg.get("waves_per_group", 0)), 0, int(cfg.get("groups_per_cu", 0)), 0)
+        p = ServerParams(self._arena_base, int(arena_bytes), max_inflight, max_batch, target_tris, max_items,
+                         c, 0, 0)
+        n = pool.mesh_count
+        self._arrs = [np.ascontiguousarray(a, MESHLET_DTYPE) for a in pool.host_meshlets]
+        ptrs = (C.c_void_p * max(n, 1))(*[a.ctypes.data if a.size else None for a in self._arrs])
+        table = np.ascontiguousarray(pool.host_table)
+        h = C.c_void_p()
+        _check(lib().gtsr_server_create(table.ctypes.data, ptrs, n, C.byref(p), C.byref(h)))
+        self._h = h
+        self._buf = np.zeros(1024, COMPLETION_DTYPE)
+
+    def submit(self, mesh: int, tag: int):
+        _check(lib().gtsr_server_submit(self._h, int(mesh), int(tag)))
+
+    def poll(self, timeout_us: int = 0) -> np.ndarray:
+        """Finished requests (``COMPLETION_DTYPE``), oldest first."""
+        cnt = C.c_uint32()
+        _check(lib().gtsr_server_poll(self._h, self._buf.ctypes.data, self._buf.size, C.byref(cnt),
+                                      int(timeout_us)))
+        return self._buf[:cnt.value].copy()
+
+    def output(self, completion):
+        """The decoded triples of a finished, unreleased request (a view into the arena)."""
+        off = self._arena_base - self.arena.data_ptr() + int(completion["out_offset"])
+        return self.arena[off:off + int(completion["out_bytes"])].view(-1, 3)
+
+    def release(self, tag: int):
+        _check(lib().gtsr_server_release(self._h, int(tag)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().gtsr_server_get_stats(self._h, C.byref(st)))
+        return {n: int(getattr(st, n)) for n, _ in ServerStats._fields_}
+
+    def replay(self, arrival_ns: np.ndarray, meshes: np.ndarray, tag_base: int = 0):
+        """Open-loop replay of an arrival trace (``gtsr_server_replay``); returns
+        ``(completions, start_ns)``."""
+        arr = np.ascontiguousarray(arrival_ns, np.uint64)
+        ms = np.ascontiguousarray(meshes, np.uint32)
+        out = np.zeros(arr.size, COMPLETION_DTYPE)
+        start = C.c_uint64()
+        _check(lib().gtsr_server_replay(self._h, arr.ctypes.data, ms.ctypes.data, arr.size, int(tag_base),
+                                        out.ctypes.data, C.byref(start)))
+        return out, int(start.value)
+
+    def close(self):
+        if self._h:
+            lib().gtsr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -21,10 +21,12 @@ ARCH = os.environ.get("GTSR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")
 
-HOST_SOURCES = ["encode.cpp", "capi.cpp"]
+HOST_SOURCES = ["encode.cpp", "capi.cpp", "tune.cpp", "serve.cpp"]
 HIP_SOURCES = ["decode.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]
+# Host files that call the HIP runtime API (autotuner, server) compile with g++.
+HIP_HOST = ["-D__HIP_PLATFORM_AMD__", "-isystem", "/opt/rocm/include"]
 # Packed FP32 instructions are kept out of all device code.
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
@@ -44,7 +46,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        jobs.append([CXX, *COMMON, "-Wall", "-Wextra", "-pthread", "-c", os.path.join(CSRC, src), "-o", obj])
+        jobs.append([CXX, *COMMON, *HIP_HOST, "-Wall", "-Wextra", "-pthread", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")

@@ -520,7 +520,9 @@ int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gts
   const uint32_t cus = cu_count();
   if (!cus) return fail(GTSR_EHIP, std::string(who) + ": cannot query the device");
   if (work_items == 0) return ok();
-  const uint32_t groups = round_up8(uint64_t(cus) * d.gpc);
+  // resident grid, or fewer groups when the list has fewer items than that grid has wavefronts
+  const uint64_t want = (uint64_t(work_items) + d.waves - 1) / d.waves;
+  const uint32_t groups = round_up8(std::min<uint64_t>(uint64_t(cus) * d.gpc, want));
   hipLaunchKernelGGL(k_decode_batched, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes, stream,
                      table, mesh_count, work, work_items);
   return check_launch(who);

@@ -193,6 +193,31 @@ def test_batched_graph_replays():
     g.close()
 
 
+def test_autotune_picks_a_measured_shape_and_keeps_outputs():
+    encs = [O.encode(m.tri, m.nverts, *caps) for m, caps in _batched_meshes()]
+    refs = [O.decode(s) for s in encs]
+    libencs = [P.encode(m.tri, m.nverts, *caps) for m, caps in _batched_meshes()]
+    pool = P.Pool(libencs)
+    pool.out.fill_(0xAA)
+    cfgs = [{"waves_per_group": 1, "groups_per_cu": 4}, {"waves_per_group": 4, "groups_per_cu": 2}]
+    say("[gpu] autotune 2 targets x 2 shapes")
+    cfg, best, points = pool.autotune(targets=[200, 3000], cfgs=cfgs, reps=3)
+    torch.cuda.synchronize()
+    assert len(points) == 4
+    assert {(p["target_tris"], p["waves_per_group"], p["groups_per_cu"]) for p in points} == \
+        {(t, c["waves_per_group"], c["groups_per_cu"]) for t in (200, 3000) for c in cfgs}
+    assert best["median_ms"] == min(p["median_ms"] for p in points)
+    assert pool.work_items == best["work_items"]
+    assert cfg == {"waves_per_group": best["waves_per_group"], "groups_per_cu": best["groups_per_cu"]}
+    for i, ref in enumerate(refs):
+        np.testing.assert_array_equal(pool.output(i).cpu().numpy(), ref)
+    pool.out.fill_(0x55)
+    pool.decode_batched(cfg=cfg)
+    torch.cuda.synchronize()
+    for i, ref in enumerate(refs):
+        np.testing.assert_array_equal(pool.output(i).cpu().numpy(), ref)
+
+
 def test_full_size_single_mesh():
     """The 5.2M-triangle icosphere (64v/126t caps) in the plain launch shape
     the benchmark uses: library stream == oracle stream, GPU decode == oracle
@@ -209,3 +234,54 @@ def test_full_size_single_mesh():
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     np.testing.assert_array_equal(got, O.decode(so))
+
+
+@pytest.mark.timeout(600)
+def test_stress_delaunay_full_size():
+    """The 200 irregular Delaunay meshes (50k-1M triangles each, 64v/126t caps),
+    library-encoded and decoded by one batched launch in the shape the
+    benchmark times (autotuned): every output byte equals the oracle's decode of
+    the same stream; two meshes also round-trip to their input triangles."""
+    import bench
+
+    threads = bench.host_threads()
+    say(f"[gpu] stress: generating 200 Delaunay meshes on {threads} threads")
+    meshes = meshgen.workload4(200, threads)
+    encs = [None] * len(meshes)
+
+    def enc(i):
+        m = meshes[i]
+        encs[i] = P.encode(m.tri, m.nverts, m.max_vertices, m.max_triangles, threads=1)
+
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(enc, range(len(meshes))))
+    tris = sum(e.stats["input_triangles"] for e in encs)
+    restarts = sum(e.stats["restarts"] for e in encs)
+    meshlets = sum(e.meshlet_count for e in encs)
+    reuse = sum(e.stats["reuse_count"] for e in encs)
+    strip = sum(e.strip_triangles for e in encs)
+    say(f"[gpu] stress: {tris} triangles, {meshlets} meshlets, {restarts / meshlets:.2f} restarts per meshlet, "
+        f"reuse fraction {reuse / strip:.3f}")
+    assert 50_000_000 < tris < 80_000_000
+    pool = P.Pool(encs)
+    pool.out.fill_(0xAA)
+    cfg, best, _ = pool.autotune(reps=2)
+    say(f"[gpu] stress: autotuned {best}")
+    pool.out.fill_(0x55)
+    g = pool.batched_graph(cfg)
+    g()
+    torch.cuda.synchronize()
+    got = pool.out.cpu().numpy()
+    for i, e in enumerate(encs):
+        a, b = int(pool.out_offsets[i]), int(pool.out_offsets[i + 1])
+        ref = O.decode_arrays(e.desc_bytes, e.bits, e.reuse, e.strip_triangles)
+        if not np.array_equal(got[a:b].reshape(-1, 3), ref):
+            bad = np.nonzero((got[a:b].reshape(-1, 3) != ref).any(axis=1))[0]
+            pytest.fail(f"stress mesh {i}: {bad.size} triangles differ, first {bad[:5]}")
+    for i in (0, 199):
+        m, e = meshes[i], encs[i]
+        a, b = int(pool.out_offsets[i]), int(pool.out_offsets[i + 1])
+        s = O.Stream(e.desc_bytes, e.bits, e.reuse, e.verts, e.vert_off, e.stats)
+        np.testing.assert_array_equal(O.round_trip_triangles(s, got[a:b].reshape(-1, 3)), O.canonical(m.tri))
+    g.close()

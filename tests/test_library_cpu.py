@@ -46,14 +46,42 @@ def test_library_exports_every_header_function():
     assert set(names) == set(P.EXPORTED)
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets, as a C compiler lays the header out."""
     import ctypes
-    assert ctypes.sizeof(P.Meshlet) == 16
-    assert ctypes.sizeof(P.EncodeParams) == 16
-    assert ctypes.sizeof(P.LaunchCfg) == 16
-    assert P.MESH_ENTRY_DTYPE.itemsize == 64
-    assert P.WORK_ITEM_DTYPE.itemsize == 16
-    assert P.MESHLET_DTYPE.itemsize == 16
+    import subprocess
+    mirrors = {
+        "gtsr_meshlet": P.Meshlet, "gtsr_encode_params": P.EncodeParams, "gtsr_encoded_view": P.EncodedView,
+        "gtsr_stream": P.StreamDesc, "gtsr_launch_cfg": P.LaunchCfg, "gtsr_tune_point": P.TunePoint,
+        "gtsr_server_params": P.ServerParams, "gtsr_server_stats": P.ServerStats,
+        "gtsr_mesh_entry": P.MESH_ENTRY_DTYPE, "gtsr_work_item": P.WORK_ITEM_DTYPE,
+        "gtsr_completion": P.COMPLETION_DTYPE,
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gtsr.h"', "int main(void) {"]
+    want = []
+    for cname, m in mirrors.items():
+        if isinstance(m, np.dtype):
+            fields = [(f, m.fields[f][1]) for f in m.names]
+            size = m.itemsize
+        else:
+            fields = [(f, getattr(m, f).offset) for f, _ in m._fields_]
+            size = ctypes.sizeof(m)
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        want.append((cname, "sizeof", size))
+        for f, off in fields:
+            cf = {"reserved0": "reserved0"}.get(f, f)
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {cf}));')
+            want.append((cname, f, off))
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert len(got) == len(want)
+    for (cname, f, w), g in zip(want, got):
+        assert g == w, f"{cname}.{f}: header {g}, binding {w}"
 
 
 def _same(so, sl):
