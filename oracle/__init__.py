@@ -2,7 +2,8 @@
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It wraps ``liboracle.so`` (plain C,
-``oracle.c``: sequential encoder, strip-walk decoder, stream checker) and
+``oracle.c``: sequential encoder, strip-walk decoders for GTS-Reuse and plain
+GTS, stream checker, degenerate compaction) and
 re-exports the pure-Python closed-form decoder from ``defn``.
 
 Nothing here imports or loads the product package or its library.
@@ -65,6 +66,13 @@ def lib():
     L.oracle_decode_meshlet.restype = C.c_int
     L.oracle_check_stream.argtypes = [vp, C.c_uint32, vp, C.c_uint64, vp, C.c_uint64, C.c_uint64]
     L.oracle_check_stream.restype = C.c_int
+    L.oracle_gts_decode.argtypes = [vp, C.c_uint32, vp, C.c_uint64, vp, C.c_uint64, vp, C.c_uint64]
+    L.oracle_gts_decode.restype = C.c_int
+    L.oracle_gts_from_reuse.argtypes = [vp, C.c_uint32, vp, C.c_uint64, vp, C.c_uint64, vp, vp, C.c_uint64,
+                                        vp, C.c_uint64]
+    L.oracle_gts_from_reuse.restype = C.c_int
+    L.oracle_compact.argtypes = [vp, C.c_uint64, vp, C.c_uint64, u64p, vp, C.c_uint32, vp]
+    L.oracle_compact.restype = C.c_int
     _lib = L
     return L
 
@@ -161,6 +169,67 @@ def decode_arrays(desc, bits, reuse, strip_triangles, out=None, m0=0, m1=None):
     if rc != OK:
         raise OracleError(rc)
     return out
+
+
+@dataclass
+class GtsStream:
+    """A plain GTS stream (host memory): descriptors, 8-byte L/R words, one
+    index byte per strip triangle after the first."""
+
+    desc: np.ndarray     # uint8[16*M]: word_off, index_off, out_off, T_s, V
+    words: np.ndarray    # uint8[8*chunks]
+    index: np.ndarray    # uint8[sum(T_s - 1)]
+    strip_triangles: int
+
+
+def gts_from_reuse(desc, bits, reuse, strip_triangles) -> GtsStream:
+    """Re-encode a GTS-Reuse stream as plain GTS (same strips and flags)."""
+    L = lib()
+    desc = np.ascontiguousarray(desc, np.uint8)
+    bits = np.ascontiguousarray(bits, np.uint8)
+    reuse = np.ascontiguousarray(reuse, np.uint8)
+    M = desc.size // 16
+    T = desc.reshape(-1, 16)[:, 12:14].copy().view("<u2").reshape(-1).astype(np.int64)
+    gdesc = np.zeros(16 * M, np.uint8)
+    words = np.zeros(bits.size // 2, np.uint8)
+    index = np.zeros(int((T - 1).sum()) if M else 0, np.uint8)
+    rc = L.oracle_gts_from_reuse(_ptr(desc), M, _ptr(bits), bits.size, _ptr(reuse), reuse.size,
+                                 _ptr(gdesc), _ptr(words), words.size, _ptr(index), index.size)
+    if rc != OK:
+        raise OracleError(rc)
+    return GtsStream(gdesc, words, index, int(strip_triangles))
+
+
+def decode_gts(g: GtsStream, out=None) -> np.ndarray:
+    """Decode a plain GTS stream by the strip walk: uint8[T_s_total, 3]."""
+    L = lib()
+    if out is None:
+        out = np.zeros((g.strip_triangles, 3), np.uint8)
+    rc = L.oracle_gts_decode(_ptr(g.desc), g.desc.size // 16, _ptr(g.words), g.words.size, _ptr(g.index),
+                             g.index.size, _ptr(out), out.size)
+    if rc != OK:
+        raise OracleError(rc)
+    return out
+
+
+def compact(decoded: np.ndarray, desc=None):
+    """Drop triples with a repeated index (restart degenerates), keeping order.
+    Returns the kept triples and, with ``desc``, each meshlet's offset among
+    them (M + 1 entries)."""
+    L = lib()
+    tris = np.ascontiguousarray(decoded, np.uint8).reshape(-1, 3)
+    out = np.zeros_like(tris)
+    kept = C.c_uint64()
+    offs = None
+    if desc is not None:
+        desc = np.ascontiguousarray(desc, np.uint8)
+        offs = np.zeros(desc.size // 16 + 1, np.uint64)
+    rc = L.oracle_compact(_ptr(tris), tris.shape[0], _ptr(out), tris.shape[0], C.byref(kept),
+                          _ptr(desc) if desc is not None else None, desc.size // 16 if desc is not None else 0,
+                          _ptr(offs) if offs is not None else None)
+    if rc != OK:
+        raise OracleError(rc)
+    return out[:kept.value], offs
 
 
 def check_stream(desc, bits, reuse, strip_triangles) -> int:

@@ -40,6 +40,19 @@
  *                        offsets, zero padding bits, increment total, reuse
  *                        entries referring to already-introduced vertices).
  *
+ *   oracle_gts_decode    The plain GTS variant of Sec. 4.2 / Fig. "Strip
+ *                        Encoding" (c): the same L/R flags, but every strip
+ *                        triangle t >= 1 stores the local index it adds as
+ *                        one byte (0,1,2 of the first triangle implicit).
+ *                        Same sequential walk as oracle_decode.
+ *   oracle_gts_from_reuse  Re-encodes a GTS-Reuse stream as plain GTS: walks
+ *                        each meshlet's index stream and writes it out.
+ *   oracle_compact       Drops the degenerate triangles of the restarts
+ *                        (Sec. 4.2: four per restart; they are the only
+ *                        triangles with a repeated index) from decoded
+ *                        triples, keeping order; reports each meshlet's
+ *                        offset among the kept triangles.
+ *
  * Stream layout parsed here (all little-endian):
  *   descriptor, 16 bytes per meshlet:
  *     u32 chunk_off   first 16-byte flag chunk of the meshlet
@@ -52,6 +65,12 @@
  *     INC bit 1 = new vertex.  Triangle 0 has no INC bit (stored 0).
  *   reuse: one byte per reused index, meshlet by meshlet.
  *   output: 3 bytes per strip triangle at byte 3*(out_off + t).
+ * Plain GTS stream layout:
+ *   descriptor, 16 bytes: u32 word_off (first 8-byte L/R word), u32 index_off
+ *     (first index byte), u32 out_off, u16 tri_count, u16 vert_count;
+ *   L/R words, 8 bytes per 64 strip triangles (bit i of word w belongs to
+ *     strip triangle 64w+i, 1 = R); bits past T_s are 0;
+ *   index bytes, T_s - 1 per meshlet: the vertex each triangle t >= 1 adds.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -200,6 +219,111 @@ int oracle_check_stream(const uint8_t* desc, uint32_t meshlet_count,
     chunk += nch; rpos += n_ru; opos += T;
   }
   if (16ull * chunk != bits_bytes || rpos != reuse_bytes || opos != strip_triangles) return OR_ECORRUPT;
+  return OR_OK;
+}
+
+/* -------------------------------------------------------------- plain GTS */
+
+static int gts_flag(const uint8_t* words, uint32_t word_off, uint32_t t) {
+  uint64_t w = rd_u64(words + 8ull * (word_off + t / 64));
+  return (int)((w >> (t % 64)) & 1u);
+}
+
+/*
+ * Decode a plain GTS stream by the strip walk of Sec. 2 / 4.2: the first
+ * triangle is (0,1,2) oriented by its flag; every later one keeps the edge
+ * its flag names and adds the vertex its index byte gives.
+ */
+int oracle_gts_decode(const uint8_t* desc, uint32_t meshlet_count,
+                      const uint8_t* words, uint64_t words_bytes,
+                      const uint8_t* index, uint64_t index_bytes,
+                      uint8_t* out, uint64_t out_bytes) {
+  for (uint32_t m = 0; m < meshlet_count; ++m) {
+    const uint8_t* d = desc + 16ull * m;
+    uint32_t word_off = rd_u32(d), index_off = rd_u32(d + 4), out_off = rd_u32(d + 8);
+    uint32_t T = rd_u16(d + 12), V = rd_u16(d + 14);
+    if (T < 1 || T > 256 || V < 3 || V > 256) return OR_ECORRUPT;
+    if (8ull * (word_off + (T + 63) / 64) > words_bytes) return OR_ECORRUPT;
+    if ((uint64_t)index_off + T - 1 > index_bytes) return OR_ECORRUPT;
+    if (3ull * ((uint64_t)out_off + T) > out_bytes) return OR_EINVAL;
+    uint32_t A, B, C;
+    if (gts_flag(words, word_off, 0) == FLAG_L) { A = 0; B = 1; } else { A = 1; B = 0; }
+    C = 2;
+    uint8_t* o = out + 3ull * out_off;
+    o[0] = (uint8_t)A; o[1] = (uint8_t)B; o[2] = (uint8_t)C;
+    for (uint32_t t = 1; t < T; ++t) {
+      uint32_t D = index[index_off + t - 1];
+      if (gts_flag(words, word_off, t) == FLAG_R) { A = C; } else { B = C; }
+      C = D;
+      o[3 * t + 0] = (uint8_t)A; o[3 * t + 1] = (uint8_t)B; o[3 * t + 2] = (uint8_t)C;
+    }
+  }
+  return OR_OK;
+}
+
+/*
+ * Plain GTS from GTS-Reuse: the same flags (the L/R word of every 16-byte
+ * chunk) and, per meshlet, the index stream I[3..T_s+1] that the reuse walk
+ * produces (next new vertex for a set increment flag, else the next reuse
+ * byte).  gdesc: 16 * meshlet_count bytes; words: 8 * chunks bytes; index:
+ * sum of (T_s - 1) bytes; each capacity is checked.
+ */
+int oracle_gts_from_reuse(const uint8_t* desc, uint32_t meshlet_count,
+                          const uint8_t* bits, uint64_t bits_bytes,
+                          const uint8_t* reuse, uint64_t reuse_bytes,
+                          uint8_t* gdesc, uint8_t* words, uint64_t words_cap,
+                          uint8_t* index, uint64_t index_cap) {
+  uint64_t ipos = 0;
+  for (uint32_t m = 0; m < meshlet_count; ++m) {
+    const uint8_t* d = desc + 16ull * m;
+    uint32_t chunk_off = rd_u32(d), reuse_off = rd_u32(d + 4), out_off = rd_u32(d + 8);
+    uint32_t T = rd_u16(d + 12), V = rd_u16(d + 14);
+    if (T < 1 || T > 256 || V < 3 || V > 256) return OR_ECORRUPT;
+    uint32_t nch = (T + 63) / 64;
+    if (16ull * (chunk_off + nch) > bits_bytes) return OR_ECORRUPT;
+    if (8ull * (chunk_off + nch) > words_cap || ipos + T - 1 > index_cap) return OR_EINVAL;
+    for (uint32_t c = 0; c < nch; ++c)
+      memcpy(words + 8ull * (chunk_off + c), bits + 16ull * (chunk_off + c), 8);
+    uint8_t* g = gdesc + 16ull * m;
+    wr_u32(g, chunk_off); wr_u32(g + 4, (uint32_t)ipos); wr_u32(g + 8, out_off);
+    wr_u16(g + 12, T); wr_u16(g + 14, V);
+    uint32_t next_new = 3;
+    uint64_t next_reuse = reuse_off;
+    for (uint32_t t = 1; t < T; ++t) {
+      uint32_t D;
+      if (flag_inc(bits, chunk_off, t)) {
+        D = next_new++;
+      } else {
+        if (next_reuse >= reuse_bytes) return OR_ECORRUPT;
+        D = reuse[next_reuse++];
+      }
+      index[ipos++] = (uint8_t)D;
+    }
+  }
+  return OR_OK;
+}
+
+/*
+ * Keep the triples of `tris` (n of them) that name three different
+ * vertices, in order, at out (capacity out_cap triples); *kept receives their
+ * number.  If desc is not NULL, offsets[m] (m = 0..meshlet_count) receives
+ * the number of kept triples before meshlet m's first output triangle.
+ */
+int oracle_compact(const uint8_t* tris, uint64_t n, uint8_t* out, uint64_t out_cap, uint64_t* kept,
+                   const uint8_t* desc, uint32_t meshlet_count, uint64_t* offsets) {
+  uint64_t k = 0;
+  uint32_t m = 0;
+  for (uint64_t t = 0; t < n; ++t) {
+    while (desc && m < meshlet_count && rd_u32(desc + 16ull * m + 8) == t) offsets[m++] = k;
+    const uint8_t* a = tris + 3 * t;
+    if (a[0] == a[1] || a[1] == a[2] || a[0] == a[2]) continue;
+    if (k >= out_cap) return OR_EINVAL;
+    memcpy(out + 3 * k, a, 3);
+    ++k;
+  }
+  while (desc && m < meshlet_count) offsets[m++] = k;
+  if (desc) offsets[meshlet_count] = k;
+  *kept = k;
   return OR_OK;
 }
 

@@ -77,3 +77,33 @@ def random_stream(rng: np.random.Generator, T: int, p_inc: float = 0.55, p_r: fl
         else:
             r.append(int(rng.integers(0, s + 1)))
     return f, g, r
+
+
+def pack_gts(meshlets):
+    """Plain GTS stream bytes. ``meshlets``: iterable of ``(f, idx)``; ``f`` has
+    length T_s, ``idx`` the T_s - 1 index bytes of triangles 1..T_s-1.  Layout:
+    16-byte descriptor ``{u32 word_off, u32 index_off, u32 out_off, u16 T_s,
+    u16 V}`` (V = 1 + largest index, at least 3), one u64 L/R word per 64 strip
+    triangles, index bytes meshlet by meshlet.  Returns ``(desc, words, index,
+    strip_triangles)``."""
+    desc, words, index = bytearray(), bytearray(), bytearray()
+    word = out = 0
+    for f, idx in meshlets:
+        T = len(f)
+        assert len(idx) == T - 1
+        V = max([2] + list(idx)) + 1
+        nw = (T + 63) // 64
+        desc += (word.to_bytes(4, "little") + len(index).to_bytes(4, "little") + out.to_bytes(4, "little") +
+                 T.to_bytes(2, "little") + V.to_bytes(2, "little"))
+        for w in range(nw):
+            lr = 0
+            for i in range(64):
+                t = 64 * w + i
+                if t < T:
+                    lr |= (f[t] & 1) << i
+            words += lr.to_bytes(8, "little")
+        index += bytes(idx)
+        word += nw
+        out += T
+    return (np.frombuffer(bytes(desc), np.uint8).copy(), np.frombuffer(bytes(words), np.uint8).copy(),
+            np.frombuffer(bytes(index), np.uint8).copy(), out)
