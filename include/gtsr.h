@@ -54,6 +54,15 @@ enum {
   GTSR_EHIP = -6          /* a HIP runtime call failed */
 };
 
+/* Stream formats (Sec. 4.2 / 4.3; Fig. "Strip Encoding" (c) and (d)). */
+enum {
+  GTSR_FORMAT_REUSE = 0,  /* GTS-Reuse: 16-byte chunks {LR, INC} + reuse bytes (the layout above) */
+  GTSR_FORMAT_GTS = 1     /* plain GTS: one 8-byte L/R word per 64 strip triangles + one index
+                             byte per strip triangle after the first (the vertex it adds; the
+                             first triangle's 0,1,2 are implicit).  Descriptors keep their
+                             layout: chunk_off counts 8-byte words, reuse_off index bytes. */
+};
+
 /* Per-meshlet descriptor, 16 bytes.  tri_count = T_s (strip triangles,
  * degenerates included, 1..256); vert_count = V (3..256); the meshlet holds
  * T_s + 2 - V reuse bytes and ceil(T_s/64) flag chunks. */
@@ -92,6 +101,9 @@ typedef struct gtsr_encoded_view {
   const uint32_t* vertices;
   const uint64_t* vert_off;     /* meshlet_count + 1 entries */
   uint64_t payload_bits, stored_bytes;
+  const uint32_t* kept_off;     /* meshlet_count + 1 entries: input triangles before meshlet m
+                                   (strip triangles minus restart degenerates); the offsets of a
+                                   compacted output (gtsr_decode_compact) */
 } gtsr_encoded_view;
 
 /* One encoded mesh.  For decode_meshlets the three pointers are device
@@ -162,6 +174,15 @@ void gtsr_encoded_free(gtsr_encoded* e);
  * vertices already introduced.  Returns OK or ECORRUPT (EINVAL on null). */
 int gtsr_validate(const gtsr_stream* host_stream);
 
+/* Re-encode a valid host GTS-Reuse stream as plain GTS (same strips, same
+ * flags; each strip triangle after the first stores the vertex it adds).
+ * Caller-owned host outputs: gdesc[meshlet_count]; words, 8 bytes per
+ * 16-byte chunk of the input (words_bytes = bits_bytes / 2); index,
+ * strip_triangles - meshlet_count bytes.  Errors: EINVAL (null pointer,
+ * capacity too small), ECORRUPT (the input fails gtsr_validate). */
+int gtsr_gts_from_reuse(const gtsr_stream* host_reuse_stream, gtsr_meshlet* gdesc, uint8_t* words,
+                        uint64_t words_bytes, uint8_t* index, uint64_t index_bytes);
+
 /* Build a triangle-balanced work list for decode_meshlets_batched.
  * host_meshlets[i] points at mesh i's host descriptor array of
  * meshlet_counts[i] entries.  Items never span two meshes and hold
@@ -192,6 +213,24 @@ int decode_meshlets(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes
 int gtsr_decode_meshlets_cfg(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes,
                              const gtsr_launch_cfg* cfg, void* hip_stream);
 
+/* decode_meshlets for a plain GTS stream (GTSR_FORMAT_GTS): dev->bits holds
+ * the 8-byte L/R words (bits_bytes a multiple of 8), dev->reuse the index
+ * bytes (reuse_bytes of them, allocation padded to 16 bytes).  Same output,
+ * alignment, skipping and error rules as decode_meshlets. */
+int gtsr_decode_gts(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, const gtsr_launch_cfg* cfg,
+                    void* hip_stream);
+
+/* Decode one mesh (format GTSR_FORMAT_REUSE or GTSR_FORMAT_GTS) into a
+ * compacted output without the restart degenerates (Sec. 4.2: four per
+ * restart, the only triangles with a repeated index): meshlet m's kept
+ * triangles land in order at triangle dev_kept_off[m].  dev_kept_off: device
+ * uint32[meshlet_count + 1], 4-byte aligned (gtsr_encoded_view.kept_off);
+ * out_bytes should be >= 3 * dev_kept_off[meshlet_count].  A meshlet whose
+ * kept range is decreasing, longer than its strip or past out_bytes is
+ * skipped.  Errors: EINVAL, EHIP. */
+int gtsr_decode_compact(const gtsr_stream* dev, uint32_t format, const uint32_t* dev_kept_off, uint8_t* dev_out,
+                        uint64_t out_bytes, const gtsr_launch_cfg* cfg, void* hip_stream);
+
 /* One plain decode launch per mesh, back to back on hip_stream: streams[i]
  * (host array of structs holding device pointers) into dev_outs[i] (host
  * array of device pointers) of out_bytes[i] bytes.  Arguments of every mesh
@@ -214,6 +253,13 @@ int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_ou
  * scratch memory.  Same skipping rule as decode_meshlets; items naming a
  * mesh >= mesh_count are skipped.  Errors: EINVAL, EHIP. */
 int decode_meshlets_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
+                            const gtsr_work_item* dev_work, uint32_t work_items,
+                            const gtsr_launch_cfg* cfg, void* hip_stream);
+
+/* decode_meshlets_batched for a table whose entries all hold plain GTS
+ * streams (bits = L/R words, bits_bytes a multiple of 8; reuse = index
+ * bytes). */
+int gtsr_decode_gts_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
                             const gtsr_work_item* dev_work, uint32_t work_items,
                             const gtsr_launch_cfg* cfg, void* hip_stream);
 

@@ -18,6 +18,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libgtsr.so")
 
 OK, EINVAL, ENOMEM, EDEGENERATE, ELIMIT, ECORRUPT, EHIP = 0, -1, -2, -3, -4, -5, -6
+FORMAT_REUSE, FORMAT_GTS = 0, 1
 
 EXPORTED = (
     "encode_meshlets", "gtsr_encoded_view_get", "gtsr_encoded_free", "gtsr_validate",
@@ -26,6 +27,7 @@ EXPORTED = (
     "gtsr_graph_destroy", "gtsr_device_cu_count", "gtsr_last_error", "gtsr_autotune_batched",
     "gtsr_server_create", "gtsr_server_submit", "gtsr_server_poll", "gtsr_server_release",
     "gtsr_server_get_stats", "gtsr_server_replay", "gtsr_server_destroy",
+    "gtsr_gts_from_reuse", "gtsr_decode_gts", "gtsr_decode_gts_batched", "gtsr_decode_compact",
 )
 
 
@@ -52,7 +54,7 @@ class EncodedView(C.Structure):
                 ("meshlets", C.c_void_p), ("bits", C.c_void_p), ("bits_bytes", C.c_uint64),
                 ("reuse", C.c_void_p), ("reuse_bytes", C.c_uint64),
                 ("vertices", C.c_void_p), ("vert_off", C.c_void_p),
-                ("payload_bits", C.c_uint64), ("stored_bytes", C.c_uint64)]
+                ("payload_bits", C.c_uint64), ("stored_bytes", C.c_uint64), ("kept_off", C.c_void_p)]
 
 
 class StreamDesc(C.Structure):
@@ -138,6 +140,10 @@ def lib():
         "gtsr_server_get_stats": (C.c_int, [vp, C.POINTER(ServerStats)]),
         "gtsr_server_replay": (C.c_int, [vp, vp, vp, u32, u64, vp, C.POINTER(u64)]),
         "gtsr_server_destroy": (None, [vp]),
+        "gtsr_gts_from_reuse": (C.c_int, [C.POINTER(StreamDesc), vp, vp, u64, vp, u64]),
+        "gtsr_decode_gts": (C.c_int, [C.POINTER(StreamDesc), vp, u64, C.POINTER(LaunchCfg), vp]),
+        "gtsr_decode_gts_batched": (C.c_int, [vp, u32, vp, u32, C.POINTER(LaunchCfg), vp]),
+        "gtsr_decode_compact": (C.c_int, [C.POINTER(StreamDesc), u32, vp, vp, u64, C.POINTER(LaunchCfg), vp]),
     }
     for name, (rt, args) in sig.items():
         f = getattr(L, name)
@@ -175,6 +181,8 @@ class Encoded:
     verts: np.ndarray         # uint32 local -> global
     vert_off: np.ndarray      # uint64[M+1]
     stats: dict = field(default_factory=dict)
+    kept_off: np.ndarray = None   # uint32[M+1]: input triangles before each meshlet
+    format: int = FORMAT_REUSE    # FORMAT_GTS: bits = 8-byte L/R words, reuse = index bytes
 
     @property
     def meshlet_count(self) -> int:
@@ -223,9 +231,29 @@ def encode(tri: np.ndarray, nverts: int, max_vertices: int = 64, max_triangles: 
         stats = {k: int(getattr(v, k)) for k in ("input_triangles", "strip_triangles", "restarts",
                                                  "reuse_count", "split_meshlets", "payload_bits",
                                                  "stored_bytes")}
+        kept_off = take(v.kept_off, M + 1, np.uint32)
     finally:
         L.gtsr_encoded_free(h)
-    return Encoded(meshlets, bits, reuse, verts, vert_off, stats)
+    return Encoded(meshlets, bits, reuse, verts, vert_off, stats, kept_off)
+
+
+def gts_from_reuse(enc: Encoded) -> Encoded:
+    """The same mesh re-encoded as plain GTS (``gtsr_gts_from_reuse``): the
+    returned ``Encoded`` has ``format == FORMAT_GTS``, ``bits`` holding the
+    8-byte L/R words and ``reuse`` the index bytes."""
+    assert enc.format == FORMAT_REUSE
+    L = lib()
+    M = enc.meshlet_count
+    gdesc = np.zeros(M, MESHLET_DTYPE)
+    words = np.zeros(enc.bits.size // 2, np.uint8)
+    index = np.zeros(max(0, enc.strip_triangles - M), np.uint8)
+    s = enc.host_stream()
+    _check(L.gtsr_gts_from_reuse(C.byref(s), gdesc.ctypes.data if M else None, words.ctypes.data if words.size else None,
+                                 words.size, index.ctypes.data if index.size else None, index.size))
+    stats = dict(enc.stats)
+    stats["stored_bytes"] = 16 * M + words.size + index.size
+    stats["payload_bits"] = enc.strip_triangles + 8 * index.size
+    return Encoded(gdesc, words, index, enc.verts, enc.vert_off, stats, enc.kept_off, FORMAT_GTS)
 
 
 def validate(enc: Encoded) -> int:
@@ -284,6 +312,7 @@ class DeviceStream:
     meshlet_count: int
     strip_triangles: int
     input_triangles: int = 0
+    format: int = FORMAT_REUSE
 
     def desc(self) -> StreamDesc:
         return StreamDesc(self.meshlets.data_ptr(), self.bits.data_ptr(), self.reuse.data_ptr(),
@@ -311,18 +340,39 @@ def upload_padded(a: np.ndarray, device="cuda"):
 def to_device(enc: Encoded, device="cuda") -> DeviceStream:
     return DeviceStream(upload_padded(enc.meshlets, device), upload_padded(enc.bits, device),
                         upload_padded(enc.reuse, device), enc.meshlet_count, enc.strip_triangles,
-                        int(enc.stats.get("input_triangles", 0)))
+                        int(enc.stats.get("input_triangles", 0)), enc.format)
 
 
 def decode(ds: DeviceStream, out=None, stream=None, cfg=None):
-    """Decode one mesh on the GPU; returns ``uint8[strip_triangles, 3]``."""
+    """Decode one mesh on the GPU (either format); returns ``uint8[strip_triangles, 3]``."""
     torch = _torch()
     L = lib()
     if out is None:
         out = torch.empty((ds.strip_triangles, 3), dtype=torch.uint8, device=ds.meshlets.device)
     d = ds.desc()
-    _check(L.gtsr_decode_meshlets_cfg(C.byref(d), out.data_ptr(), out.numel(), _cfg(cfg),
-                                      _stream_handle(stream)))
+    f = L.gtsr_decode_gts if ds.format == FORMAT_GTS else L.gtsr_decode_meshlets_cfg
+    _check(f(C.byref(d), out.data_ptr(), out.numel(), _cfg(cfg), _stream_handle(stream)))
+    return out
+
+
+def decode_compact(ds: DeviceStream, kept_off, out=None, stream=None, cfg=None):
+    """Decode one mesh without its restart degenerates (``gtsr_decode_compact``).
+    ``kept_off``: uint32[M+1] kept offsets (numpy or a device tensor); returns
+    ``uint8[kept_off[M], 3]``."""
+    torch = _torch()
+    L = lib()
+    if isinstance(kept_off, np.ndarray):
+        kept_host = np.ascontiguousarray(kept_off, np.uint32)
+        kept_dev = torch.from_numpy(kept_host.view(np.int32).copy()).to(ds.meshlets.device)
+        total = int(kept_host[-1]) if kept_host.size else 0
+    else:
+        kept_dev = kept_off
+        total = int(kept_off[-1].item()) if kept_off.numel() else 0
+    if out is None:
+        out = torch.empty((total, 3), dtype=torch.uint8, device=ds.meshlets.device)
+    d = ds.desc()
+    _check(L.gtsr_decode_compact(C.byref(d), ds.format, kept_dev.data_ptr(), out.data_ptr(), out.numel(),
+                                 _cfg(cfg), _stream_handle(stream)))
     return out
 
 
@@ -415,6 +465,10 @@ class Pool:
 
         n = len(encs)
         self.mesh_count = n
+        formats = {e.format for e in encs}
+        if len(formats) > 1:
+            raise ValueError("a Pool holds streams of one format")
+        self.format = formats.pop() if formats else FORMAT_REUSE
         self.meshlet_counts = np.array([e.meshlet_count for e in encs], np.uint32)
         self.strip_tris = np.array([e.strip_triangles for e in encs], np.uint64)
         self.input_tris = np.array([e.stats["input_triangles"] for e in encs], np.uint64)
@@ -481,6 +535,8 @@ class Pool:
         re-plan with the fastest target and return ``(best_cfg, best, points)``:
         ``best_cfg`` is a dict for ``decode_batched`` / ``batched_graph``,
         ``best`` and ``points`` are ``TunePoint.as_dict()`` records."""
+        if self.format != FORMAT_REUSE:
+            raise ValueError("the autotuner measures GTS-Reuse pools")
         L = lib()
         n = self.mesh_count
         arrs = [np.ascontiguousarray(a, MESHLET_DTYPE) for a in self.host_meshlets]
@@ -504,10 +560,13 @@ class Pool:
     def decode_batched(self, stream=None, cfg=None):
         if self.work is None:
             self.plan()
-        _check(lib().decode_meshlets_batched(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
+        f = lib().gtsr_decode_gts_batched if self.format == FORMAT_GTS else lib().decode_meshlets_batched
+        _check(f(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
                                              self.work_items, _cfg(cfg), _stream_handle(stream)))
 
     def batched_graph(self, cfg=None):
+        if self.format != FORMAT_REUSE:
+            raise ValueError("graph capture covers GTS-Reuse pools")
         if self.work is None:
             self.plan()
         h = C.c_void_p()

@@ -92,6 +92,36 @@ extern "C" int gtsr_validate(const gtsr_stream* s) {
   return ok();
 }
 
+// Plain GTS from GTS-Reuse: the L/R word of every chunk, and per meshlet the
+// index stream after the first triangle -- the next new vertex (3, 4, ...)
+// where the increment flag is set, else the next reuse byte (Sec. 4.3).
+extern "C" int gtsr_gts_from_reuse(const gtsr_stream* s, gtsr_meshlet* gdesc, uint8_t* words, uint64_t words_bytes,
+                                   uint8_t* index, uint64_t index_bytes) {
+  if (!s) return fail(GTSR_EINVAL, "gtsr_gts_from_reuse: null stream");
+  if (int rc = gtsr_validate(s)) return rc;
+  if (s->meshlet_count && (!gdesc || !words || (s->strip_triangles > s->meshlet_count && !index)))
+    return fail(GTSR_EINVAL, "gtsr_gts_from_reuse: null output");
+  if (words_bytes < s->bits_bytes / 2 || index_bytes < s->strip_triangles - s->meshlet_count)
+    return fail(GTSR_EINVAL, "gtsr_gts_from_reuse: output too small");
+  uint64_t ipos = 0;
+  for (uint32_t m = 0; m < s->meshlet_count; ++m) {
+    const gtsr_meshlet& d = s->meshlets[m];
+    const uint32_t T = d.tri_count, nch = chunks_of(T);
+    const uint8_t* cb = s->bits + uint64_t(d.chunk_off) * kChunkBytes;
+    for (uint32_t c = 0; c < nch; ++c) std::memcpy(words + 8ull * (d.chunk_off + c), cb + 16 * c, 8);
+    gtsr_meshlet g = d;
+    g.reuse_off = static_cast<uint32_t>(ipos);
+    gdesc[m] = g;
+    uint32_t next_new = 3;
+    uint64_t r = d.reuse_off;
+    for (uint32_t t = 1; t < T; ++t) {
+      const uint64_t inc = load_u64(cb + 16 * (t / 64) + 8);
+      index[ipos++] = ((inc >> (t % 64)) & 1) ? static_cast<uint8_t>(next_new++) : s->reuse[r++];
+    }
+  }
+  return ok();
+}
+
 // Consecutive meshlets of one mesh are grouped until they reach target_tris
 // strip triangles; an item never crosses a mesh boundary.
 extern "C" int gtsr_plan_batch(const gtsr_meshlet* const* host_meshlets, const uint32_t* meshlet_counts,

@@ -108,14 +108,22 @@ __device__ __forceinline__ void store16(__amdgpu_buffer_rsrc_t r, uint32_t off, 
   __builtin_amdgcn_raw_buffer_store_b128(v, r, int(off), 0, 0);
 }
 
+// One mesh's stream.  GTS-Reuse: `bits` holds 16-byte chunks {LR, INC},
+// `reuse` the reuse bytes.  Plain GTS: `bits` holds one 8-byte L/R word per
+// chunk, `reuse` one index byte per strip triangle after the first.  With a
+// compacted output, `kept` holds the M + 1 per-meshlet offsets among the
+// non-degenerate triangles and `out_tris` counts output triangles of that
+// output.
 struct Stream {
   const uint8_t* meshlets;
   const uint8_t* bits;
   const uint8_t* reuse;
   uint8_t* out;
+  const uint32_t* kept;
   uint32_t chunks;        // the array sizes, clipped to 32 bits (offsets are 32-bit)
   uint32_t reuse_bytes;
   uint32_t out_tris;
+  uint32_t meshlet_count;
 };
 
 __device__ __forceinline__ uint32_t clip32(uint64_t v) { return v > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(v); }
@@ -127,10 +135,11 @@ struct Flags {
   uint64_t lr, inc;
 };
 
+template <bool kPlain>
 __device__ __forceinline__ Flags chunk_flags(const uint4& bv, uint32_t idx) {
   Flags f;
   f.lr = (uint64_t(lane_value(bv.y, idx)) << 32) | lane_value(bv.x, idx);
-  f.inc = (uint64_t(lane_value(bv.w, idx)) << 32) | lane_value(bv.z, idx);
+  f.inc = kPlain ? 0ull : (uint64_t(lane_value(bv.w, idx)) << 32) | lane_value(bv.z, idx);
   return f;
 }
 
@@ -146,9 +155,18 @@ struct LanePtrs {
 // minus increments below).  inc_base: 2 + increments before this chunk,
 // triangle 0 counted as introducing vertex 2; reuse_pos: reuse slots before
 // this chunk plus the meshlet's tile offset.
-template <uint32_t C>
+//
+// Plain GTS stores that slot directly: index byte t - 1 of the meshlet (its
+// tile offset is reuse_pos), triangle 0's slot being the implicit 2.
+template <bool kPlain, uint32_t C>
 __device__ __forceinline__ uint32_t new_index(const LanePtrs& lp, const Flags& f, uint32_t& inc_base,
-                                              uint32_t& reuse_pos) {
+                                              uint32_t& reuse_pos, uint32_t lane) {
+  if constexpr (kPlain) {
+    const uint32_t b = lp.reuse[reuse_pos + 64 * C - 1];   // lane 0 of chunk 0 reads a byte it ignores
+    const uint32_t N = (C == 0 && lane == 0) ? 2u : b;
+    lp.idx[64 * C + 2] = uint8_t(N);
+    return N;
+  }
   const uint64_t inc = C == 0 ? (f.inc | 1) : f.inc;
   const uint32_t ones = __builtin_amdgcn_mbcnt_hi(uint32_t(inc >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(inc), 0u));
   const uint32_t fresh = ones + inc_base;
@@ -165,10 +183,15 @@ __device__ __forceinline__ uint32_t new_index(const LanePtrs& lp, const Flags& f
 // oriented triple, written at out_m + 3t.  In chunk 0 the change word gets
 // bit 0 set: "no flip so far" then lands on position 0, whose vertex I[0] is
 // the right pivot.
-template <uint32_t C>
+//
+// Compacted output: only the lanes whose triple names three different
+// vertices (every triangle but the four degenerates of each restart) and
+// that lie inside the meshlet write, packed in order from kept_pos; the
+// others write to the tile's spare bytes past the longest shifted run.
+template <uint32_t C, bool kCompact>
 __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t* idx0, uint8_t* out_m,
                                               const Flags& f, uint32_t N, uint32_t lane, uint32_t& last_change,
-                                              uint64_t& prev_top) {
+                                              uint64_t& prev_top, uint32_t T, uint32_t& kept_pos) {
   uint64_t ch = f.lr ^ ((f.lr << 1) | prev_top);
   if (C == 0) ch |= 1;
   const uint64_t upto = ch << (63 - lane);
@@ -180,7 +203,16 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
   const uint32_t P = at_t[1];
   const uint32_t X = *px;
   const bool right = __builtin_amdgcn_inverse_ballot_w64(f.lr);
-  uint8_t* o = out_m + 192 * C;
+  uint8_t* o;
+  if constexpr (kCompact) {
+    const bool keep = 64 * C + lane < T && X != P && P != N && X != N;
+    const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(km >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(km), 0u));
+    o = keep ? out_m + 3 * (kept_pos + below) : lp.out + 3 * kRunTris + 16;   // past any shifted run
+    kept_pos += uint32_t(__builtin_popcountll(km));
+  } else {
+    o = out_m + 192 * C;
+  }
   o[0] = uint8_t(right ? P : X);
   o[1] = uint8_t(right ? X : P);
   o[2] = uint8_t(N);
@@ -192,27 +224,31 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
 // whatever its size.  Lanes past T_s compute garbage that lands past the
 // meshlet's output (the next meshlet overwrites it, or it lies past the run
 // and is never stored).
-template <uint32_t NCH>
+//
+// Compacted output: ob addresses the meshlet's first kept triangle and T
+// (its strip triangles) bounds the lanes that may write.
+template <uint32_t NCH, bool kPlain, bool kCompact>
 __device__ __forceinline__ void decode_meshlet(RunTile& tile, const LanePtrs& lp, const uint4& bv, uint32_t co,
-                                               uint32_t ro, uint32_t ob, uint32_t lane) {
-  Flags f0 = chunk_flags(bv, co), f1{0, 0}, f2{0, 0}, f3{0, 0};
-  if constexpr (NCH > 1) f1 = chunk_flags(bv, co + 1);
-  if constexpr (NCH > 2) f2 = chunk_flags(bv, co + 2);
-  if constexpr (NCH > 3) f3 = chunk_flags(bv, co + 3);
+                                               uint32_t ro, uint32_t ob, uint32_t lane, uint32_t T) {
+  Flags f0 = chunk_flags<kPlain>(bv, co), f1{0, 0}, f2{0, 0}, f3{0, 0};
+  if constexpr (NCH > 1) f1 = chunk_flags<kPlain>(bv, co + 1);
+  if constexpr (NCH > 2) f2 = chunk_flags<kPlain>(bv, co + 2);
+  if constexpr (NCH > 3) f3 = chunk_flags<kPlain>(bv, co + 3);
   uint32_t inc_base = 2, reuse_pos = ro;
-  const uint32_t n0 = new_index<0>(lp, f0, inc_base, reuse_pos);
+  const uint32_t n0 = new_index<kPlain, 0>(lp, f0, inc_base, reuse_pos, lane);
   uint32_t n1 = 0, n2 = 0, n3 = 0;
-  if constexpr (NCH > 1) n1 = new_index<1>(lp, f1, inc_base, reuse_pos);
-  if constexpr (NCH > 2) n2 = new_index<2>(lp, f2, inc_base, reuse_pos);
-  if constexpr (NCH > 3) n3 = new_index<3>(lp, f3, inc_base, reuse_pos);
+  if constexpr (NCH > 1) n1 = new_index<kPlain, 1>(lp, f1, inc_base, reuse_pos, lane);
+  if constexpr (NCH > 2) n2 = new_index<kPlain, 2>(lp, f2, inc_base, reuse_pos, lane);
+  if constexpr (NCH > 3) n3 = new_index<kPlain, 3>(lp, f3, inc_base, reuse_pos, lane);
   wave_lds_sync();
-  uint8_t* out_m = lp.out + ob;
-  uint32_t last_change = 0;
+  // lane-relative output (lp.out = tile + 3 * lane), or the tile base when compacting
+  uint8_t* out_m = kCompact ? reinterpret_cast<uint8_t*>(tile.out) + ob : lp.out + ob;
+  uint32_t last_change = 0, kept_pos = 0;
   uint64_t prev_top = 0;
-  emit_triangle<0>(lp, tile.idx, out_m, f0, n0, lane, last_change, prev_top);
-  if constexpr (NCH > 1) emit_triangle<1>(lp, tile.idx, out_m, f1, n1, lane, last_change, prev_top);
-  if constexpr (NCH > 2) emit_triangle<2>(lp, tile.idx, out_m, f2, n2, lane, last_change, prev_top);
-  if constexpr (NCH > 3) emit_triangle<3>(lp, tile.idx, out_m, f3, n3, lane, last_change, prev_top);
+  emit_triangle<0, kCompact>(lp, tile.idx, out_m, f0, n0, lane, last_change, prev_top, T, kept_pos);
+  if constexpr (NCH > 1) emit_triangle<1, kCompact>(lp, tile.idx, out_m, f1, n1, lane, last_change, prev_top, T, kept_pos);
+  if constexpr (NCH > 2) emit_triangle<2, kCompact>(lp, tile.idx, out_m, f2, n2, lane, last_change, prev_top, T, kept_pos);
+  if constexpr (NCH > 3) emit_triangle<3, kCompact>(lp, tile.idx, out_m, f3, n3, lane, last_change, prev_top, T, kept_pos);
   wave_lds_sync();
 }
 
@@ -225,7 +261,7 @@ struct Plan {
   uint32_t c0, r0, o0;    // first flag chunk, reuse byte, output triangle
   uint32_t nch;           // flag chunks
   uint32_t ra, nrb;       // reuse staging start (16-byte aligned) and 16-byte blocks
-  uint32_t tris;          // strip triangles
+  uint32_t tris;          // output triangles (strip triangles, or kept ones when compacting)
 };
 
 // Per-lane layout of meshlet `lane` in the run's tile, one word:
@@ -242,12 +278,28 @@ __device__ __forceinline__ uint4 load_descriptors(const Stream& s, uint32_t m, u
   return load16(buffer(s.meshlets + 16ull * m, 16 * cnt), 16 * lane);
 }
 
-__device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, uint32_t m, uint32_t m_end, uint32_t lane,
-                                          uint32_t& layout) {
+// Kept offsets of the same meshlets and of the one after each (compacted
+// output): lane i gets kept[m + i] and kept[m + i + 1]; m_end <= M, so both
+// stay inside the M + 1 entries.
+__device__ __forceinline__ uint2 load_kept(const Stream& s, uint32_t m, uint32_t m_end, uint32_t lane) {
+  const uint32_t cnt = m < m_end ? min(m_end - m, kRunMeshlets) : 0u;
+  const __amdgpu_buffer_rsrc_t r = buffer(s.kept + m, 4 * (cnt + (cnt ? 1 : 0)));
+  const uint32_t a = uint32_t(__builtin_amdgcn_raw_buffer_load_b32(r, int(4 * lane), 0, 0));
+  const uint32_t b = uint32_t(__builtin_amdgcn_raw_buffer_load_b32(r, int(4 * lane + 4), 0, 0));
+  return make_uint2(a, b);
+}
+
+// Validates the descriptors (and kept offsets kd) and takes the leading run of
+// usable meshlets.  layout: the per-lane word above; with a compacted output
+// its output field is the kept offset inside the run, and o0 names the run's
+// first kept triangle.
+template <bool kPlain, bool kCompact>
+__device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, const uint2& kd, uint32_t m,
+                                          uint32_t m_end, uint32_t lane, uint32_t& layout) {
   const uint32_t cnt = m < m_end ? min(m_end - m, kRunMeshlets) : 0u;
   const uint32_t T = d.w & 0xFFFFu, V = d.w >> 16;
   const uint32_t nch = (T + 63) >> 6;
-  const uint32_t nru = T + 2 - V;
+  const uint32_t nru = kPlain ? T - 1 : T + 2 - V;   // reuse bytes, or index bytes
   Plan p;
   p.c0 = uniform(d.x);
   p.r0 = uniform(d.y);
@@ -255,28 +307,46 @@ __device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, uint3
   p.ra = p.r0 & ~15u;
   // counts in range, arrays not overrun (overflow-free forms)
   bool ok = lane < cnt && T - 1u < kMaxStripTris && V >= 3 && V <= 256 && V <= T + 2;
-  ok = ok && d.x <= s.chunks && nch <= s.chunks - d.x && d.y <= s.reuse_bytes && nru <= s.reuse_bytes - d.y &&
-       d.z <= s.out_tris && T <= s.out_tris - d.z;
+  ok = ok && d.x <= s.chunks && nch <= s.chunks - d.x && d.y <= s.reuse_bytes && nru <= s.reuse_bytes - d.y;
   // contiguous with the meshlet before it (lane 0 starts the run)
   const uint32_t ex = d.x + nch, ey = d.y + nru, ez = d.z + T;
   const uint32_t px = from_lane_below(ex), py = from_lane_below(ey), pz = from_lane_below(ez);
   ok = ok && (lane == 0 || (d.x == px && d.y == py && d.z == pz));
   // the run still fits the tile
   ok = ok && ex - p.c0 <= kRunChunks && ey - p.ra <= kReuseStage && ez - p.o0 <= kRunTris;
+  uint32_t ot = d.z - p.o0;
+  if constexpr (kCompact) {
+    // kept triangles: no more than the strip triangles, so kept positions stay
+    // at or before the strip positions inside the tile; the output holds them
+    const uint32_t kf = uniform(kd.x);
+    ok = ok && kd.y >= kd.x && kd.y - kd.x <= T && kd.x - kf <= d.z - p.o0 && kd.y <= s.out_tris;
+    ot = kd.x - kf;
+    p.o0 = kf;
+  } else {
+    ok = ok && d.z <= s.out_tris && T <= s.out_tris - d.z;
+  }
   const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
   p.k = uint32_t(__builtin_ctzll(~okm));   // leading run of usable meshlets (okm has no bit past lane 31)
-  layout = pack_layout(d.x - p.c0, d.y - p.ra, d.z - p.o0, nch);
+  layout = pack_layout(d.x - p.c0, d.y - p.ra, ot, nch);
   if (p.k) {
     p.nch = lane_value(ex, p.k - 1) - p.c0;
     p.nrb = (lane_value(ey, p.k - 1) - p.ra + 15) >> 4;
-    p.tris = lane_value(ez, p.k - 1) - p.o0;
+    p.tris = (kCompact ? lane_value(kd.y, p.k - 1) : lane_value(ez, p.k - 1)) - p.o0;
   } else {
     p.nch = p.nrb = p.tris = 0;
   }
   return p;
 }
 
+// GTS-Reuse: one 16-byte chunk per lane.  Plain GTS: one 8-byte L/R word per lane.
+template <bool kPlain>
 __device__ __forceinline__ uint4 load_bits(const Stream& s, const Plan& p, uint32_t lane) {
+  if constexpr (kPlain) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 v = __builtin_bit_cast(
+        u32x2, __builtin_amdgcn_raw_buffer_load_b64(buffer(s.bits + 8ull * p.c0, 8 * p.nch), int(8 * lane), 0, 0));
+    return make_uint4(v.x, v.y, 0, 0);
+  }
   return load16(buffer(s.bits + 16ull * p.c0, 16 * p.nch), 16 * lane);
 }
 
@@ -286,19 +356,22 @@ __device__ __forceinline__ uint4 load_reuse(const Stream& s, const Plan& p, uint
   return load16(buffer(s.reuse + p.ra, 16 * p.nrb), 16 * lane);
 }
 
-// Decodes the run's meshlets from the tile.
+// Decodes the run's meshlets from the tile.  tri_counts: lane i holds meshlet
+// i's T_s (read only when compacting).
+template <bool kPlain, bool kCompact>
 __device__ __forceinline__ void decode_run(RunTile& tile, const LanePtrs& lp, const Plan& p, uint32_t layout,
-                                           const uint4& bv, uint32_t shift, uint32_t lane) {
+                                           uint32_t tri_counts, const uint4& bv, uint32_t shift, uint32_t lane) {
   for (uint32_t i = 0; i < p.k; ++i) {
     const uint32_t w = lane_value(layout, i);
     const uint32_t co = w & 63u, ro = (w >> 6) & 2047u, ob = shift + 3 * ((w >> 17) & 4095u);
     const uint32_t nch = (w >> 29) + 1;
+    const uint32_t T = kCompact ? lane_value(tri_counts, i) : 0u;
     if (nch > 2) {
-      if (nch > 3) decode_meshlet<4>(tile, lp, bv, co, ro, ob, lane);
-      else decode_meshlet<3>(tile, lp, bv, co, ro, ob, lane);
+      if (nch > 3) decode_meshlet<4, kPlain, kCompact>(tile, lp, bv, co, ro, ob, lane, T);
+      else decode_meshlet<3, kPlain, kCompact>(tile, lp, bv, co, ro, ob, lane, T);
     } else {
-      if (nch > 1) decode_meshlet<2>(tile, lp, bv, co, ro, ob, lane);
-      else decode_meshlet<1>(tile, lp, bv, co, ro, ob, lane);
+      if (nch > 1) decode_meshlet<2, kPlain, kCompact>(tile, lp, bv, co, ro, ob, lane, T);
+      else decode_meshlet<1, kPlain, kCompact>(tile, lp, bv, co, ro, ob, lane, T);
     }
   }
 }
@@ -342,15 +415,18 @@ __device__ __forceinline__ void store_nothing(uint8_t* any) {
 }
 
 // Decodes meshlets [m, m_end) of stream s with the calling wavefront.
+template <bool kPlain, bool kCompact>
 __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32_t m_end, RunTile& tile,
                                              const LanePtrs& lp, uint32_t lane) {
   if (m >= m_end) return;
   uint4 d = load_descriptors(s, m, m_end, lane);
+  uint2 kd = kCompact ? load_kept(s, m, m_end, lane) : make_uint2(0, 0);
   uint32_t layout;
-  Plan p = make_plan(s, d, m, m_end, lane, layout);
+  Plan p = make_plan<kPlain, kCompact>(s, d, kd, m, m_end, lane, layout);
   uint32_t mn = m + (p.k ? p.k : 1);
   uint4 dn = load_descriptors(s, mn, m_end, lane);
-  uint4 bv = load_bits(s, p, lane);
+  uint2 kdn = kCompact ? load_kept(s, mn, m_end, lane) : make_uint2(0, 0);
+  uint4 bv = load_bits<kPlain>(s, p, lane);
   uint4 rv = load_reuse(s, p, lane);
   store_nothing(s.out);
   for (;;) {
@@ -358,21 +434,25 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
     reinterpret_cast<uint4*>(tile.reuse)[lane] = rv;
     // plan the next run and start its loads; they overlap this run's decode
     uint32_t layout_n;
-    const Plan pn = make_plan(s, dn, mn, m_end, lane, layout_n);
+    const Plan pn = make_plan<kPlain, kCompact>(s, dn, kdn, mn, m_end, lane, layout_n);
     const uint32_t mnn = mn + (pn.k ? pn.k : 1);
+    const uint32_t tri_counts = d.w & 0xFFFFu;
     const uint4 dnn = load_descriptors(s, mnn, m_end, lane);
-    const uint4 bvn = load_bits(s, pn, lane);
+    const uint2 kdnn = kCompact ? load_kept(s, mnn, m_end, lane) : make_uint2(0, 0);
+    const uint4 bvn = load_bits<kPlain>(s, pn, lane);
     const uint4 rvn = load_reuse(s, pn, lane);
     wave_lds_sync();
     uint8_t* dst = s.out + 3ull * p.o0;
     const uint32_t shift = uint32_t(reinterpret_cast<uintptr_t>(dst)) & 15u;
-    decode_run(tile, lp, p, layout, bv, shift, lane);
+    decode_run<kPlain, kCompact>(tile, lp, p, layout, tri_counts, bv, shift, lane);
     store_run(dst, shift, p.tris, tile, lane);
     wave_lds_sync();
     if (mn >= m_end) break;
     p = pn;
     layout = layout_n;
+    d = dn;
     dn = dnn;
+    kdn = kdnn;
     bv = bvn;
     rv = rvn;
     mn = mnn;
@@ -403,10 +483,13 @@ __device__ __forceinline__ void wave_block(uint64_t n, uint32_t wave, uint32_t w
 }
 
 // Plain decoder: every wavefront decodes one contiguous block of meshlets.
+// kPlain: plain GTS stream; kCompact: degenerate triangles dropped, kept
+// offsets in `kept`, out_tris counting output triangles.
+template <bool kPlain, bool kCompact>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
     const gtsr_meshlet* __restrict__ meshlets, const uint8_t* __restrict__ bits,
-    const uint8_t* __restrict__ reuse, uint8_t* __restrict__ out, uint32_t meshlet_count,
-    uint64_t chunks, uint64_t reuse_bytes, uint64_t out_tris) {
+    const uint8_t* __restrict__ reuse, uint8_t* __restrict__ out, const uint32_t* __restrict__ kept,
+    uint32_t meshlet_count, uint64_t chunks, uint64_t reuse_bytes, uint64_t out_tris) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = uniform(threadIdx.x / kWave);
   LanePtrs lp;
@@ -414,14 +497,16 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
   uint64_t b0, b1;
   wave_block(meshlet_count, wave, blockDim.x / kWave, b0, b1);
   if (b0 >= b1) return;
-  const Stream s{reinterpret_cast<const uint8_t*>(meshlets), bits, reuse, out,
-                 clip32(chunks), clip32(reuse_bytes), clip32(out_tris)};
-  decode_range(s, uint32_t(b0), uint32_t(b1), tile, lp, lane);
+  const Stream s{reinterpret_cast<const uint8_t*>(meshlets), bits, reuse, out, kept,
+                 clip32(chunks), clip32(reuse_bytes), clip32(out_tris), meshlet_count};
+  decode_range<kPlain, kCompact>(s, uint32_t(b0), uint32_t(b1), tile, lp, lane);
 }
 
 // Persistent batched decoder: every wavefront takes one contiguous block of
 // the work list (items are balanced by strip triangles) and decodes it as
 // meshlet ranges, merging consecutive items that continue the same mesh.
+// kPlain: every entry holds a plain GTS stream.
+template <bool kPlain>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
     const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
     const gtsr_work_item* __restrict__ work, uint32_t work_items) {
@@ -454,10 +539,11 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
       if ((reinterpret_cast<uintptr_t>(e.meshlets) | reinterpret_cast<uintptr_t>(e.bits) |
            reinterpret_cast<uintptr_t>(e.reuse)) & 15)
         continue;   // misaligned arrays: the entry is skipped
-      const Stream s{reinterpret_cast<const uint8_t*>(e.meshlets), e.bits, e.reuse, e.out,
-                     clip32(e.bits_bytes / 16), clip32(e.reuse_bytes), clip32(e.strip_triangles)};
+      const Stream s{reinterpret_cast<const uint8_t*>(e.meshlets), e.bits, e.reuse, e.out, nullptr,
+                     clip32(e.bits_bytes / (kPlain ? 8 : 16)), clip32(e.reuse_bytes), clip32(e.strip_triangles),
+                     e.meshlet_count};
       const uint32_t stop = min(end, e.meshlet_count);
-      if (first < stop) decode_range(s, first, stop, tile, lp, lane);
+      if (first < stop) decode_range<kPlain, false>(s, first, stop, tile, lp, lane);
     }
   }
 }
@@ -509,7 +595,8 @@ int check_launch(const char* who) {
 inline uint32_t round_up8(uint64_t g) { return uint32_t((g + kXcds - 1) / kXcds * kXcds); }
 
 int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gtsr_work_item* work,
-                    uint32_t work_items, const gtsr_launch_cfg* cfg, hipStream_t stream, const char* who) {
+                    uint32_t work_items, const gtsr_launch_cfg* cfg, hipStream_t stream, const char* who,
+                    bool plain = false) {
   if ((mesh_count && !table) || (work_items && !work)) return fail(GTSR_EINVAL, std::string(who) + ": null pointer");
   if ((reinterpret_cast<uintptr_t>(table) & 15) || (reinterpret_cast<uintptr_t>(work) & 15))
     return fail(GTSR_EINVAL, std::string(who) + ": tables must be 16-byte aligned");
@@ -523,17 +610,21 @@ int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gts
   // resident grid, or fewer groups when the list has fewer items than that grid has wavefronts
   const uint64_t want = (uint64_t(work_items) + d.waves - 1) / d.waves;
   const uint32_t groups = round_up8(std::min<uint64_t>(uint64_t(cus) * d.gpc, want));
-  hipLaunchKernelGGL(k_decode_batched, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes, stream,
-                     table, mesh_count, work, work_items);
+  if (plain)
+    hipLaunchKernelGGL(k_decode_batched<true>, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes, stream,
+                       table, mesh_count, work, work_items);
+  else
+    hipLaunchKernelGGL(k_decode_batched<false>, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes, stream,
+                       table, mesh_count, work, work_items);
   return check_launch(who);
 }
 
-int check_plain_args(const gtsr_stream* dev, const uint8_t* dev_out, uint64_t out_bytes) {
+int check_plain_args(const gtsr_stream* dev, const uint8_t* dev_out, uint64_t out_bytes, bool compact = false) {
   if (!dev) return fail(GTSR_EINVAL, "decode_meshlets: null stream");
   if (dev->meshlet_count == 0) return GTSR_OK;
   if (!dev->meshlets || !dev->bits || !dev_out || (dev->reuse_bytes && !dev->reuse))
     return fail(GTSR_EINVAL, "decode_meshlets: null device pointer");
-  if (out_bytes / 3 < dev->strip_triangles)
+  if (!compact && out_bytes / 3 < dev->strip_triangles)
     return fail(GTSR_EINVAL, "decode_meshlets: out_bytes < 3 * strip_triangles");
   if ((reinterpret_cast<uintptr_t>(dev->meshlets) | reinterpret_cast<uintptr_t>(dev->bits) |
        reinterpret_cast<uintptr_t>(dev->reuse)) & 15)
@@ -543,15 +634,27 @@ int check_plain_args(const gtsr_stream* dev, const uint8_t* dev_out, uint64_t ou
 
 // Grid: one wave per mpw meshlets, capped at groups_per_cu resident groups
 // per CU (each wave then takes a larger contiguous block).
+// plain: plain GTS stream (8-byte L/R words); kept: compacted output.
 int launch_plain(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, const Defaults& d,
-                 uint32_t cus, hipStream_t stream) {
+                 uint32_t cus, hipStream_t stream, bool plain = false, const uint32_t* kept = nullptr) {
   if (dev->meshlet_count == 0) return GTSR_OK;
   const uint64_t waves = (uint64_t(dev->meshlet_count) + d.mpw - 1) / d.mpw;
   uint64_t groups = (waves + d.waves - 1) / d.waves;
   groups = std::min<uint64_t>(groups, uint64_t(cus) * d.gpc);
-  hipLaunchKernelGGL(k_decode_plain, dim3(round_up8(groups)), dim3(kWave * d.waves), d.waves * kTileBytes, stream,
-                     dev->meshlets, dev->bits, dev->reuse, dev_out, dev->meshlet_count, dev->bits_bytes / 16,
-                     dev->reuse_bytes, out_bytes / 3);
+  const dim3 grid(round_up8(groups)), block(kWave * d.waves);
+  const uint32_t lds = d.waves * kTileBytes;
+  const uint64_t chunks = dev->bits_bytes / (plain ? 8 : 16);
+#define GTSR_LAUNCH_PLAIN(P, K)                                                                                   \
+  hipLaunchKernelGGL((k_decode_plain<P, K>), grid, block, lds, stream, dev->meshlets, dev->bits, dev->reuse, dev_out, \
+                     kept, dev->meshlet_count, chunks, dev->reuse_bytes, out_bytes / 3)
+  if (plain) {
+    if (kept) GTSR_LAUNCH_PLAIN(true, true);
+    else GTSR_LAUNCH_PLAIN(true, false);
+  } else {
+    if (kept) GTSR_LAUNCH_PLAIN(false, true);
+    else GTSR_LAUNCH_PLAIN(false, false);
+  }
+#undef GTSR_LAUNCH_PLAIN
   return GTSR_OK;
 }
 
@@ -589,6 +692,45 @@ extern "C" int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* co
 
 extern "C" int decode_meshlets(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, void* hip_stream) {
   return gtsr_decode_meshlets_cfg(dev, dev_out, out_bytes, nullptr, hip_stream);
+}
+
+extern "C" int gtsr_decode_gts(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, const gtsr_launch_cfg* cfg,
+                               void* hip_stream) {
+  if (int rc = check_plain_args(dev, dev_out, out_bytes)) return rc;
+  if (dev->bits_bytes % 8) return fail(GTSR_EINVAL, "gtsr_decode_gts: bits_bytes must be a multiple of 8");
+  Defaults d;
+  if (int rc = resolve_cfg(cfg, d, "gtsr_decode_gts")) return rc;
+  const uint32_t cus = cu_count();
+  if (!cus) return fail(GTSR_EHIP, "gtsr_decode_gts: cannot query the device");
+  launch_plain(dev, dev_out, out_bytes, d, cus, static_cast<hipStream_t>(hip_stream), true);
+  return check_launch("gtsr_decode_gts");
+}
+
+extern "C" int gtsr_decode_compact(const gtsr_stream* dev, uint32_t format, const uint32_t* dev_kept_off,
+                                   uint8_t* dev_out, uint64_t out_bytes, const gtsr_launch_cfg* cfg,
+                                   void* hip_stream) {
+  const char* who = "gtsr_decode_compact";
+  if (format != GTSR_FORMAT_REUSE && format != GTSR_FORMAT_GTS) return fail(GTSR_EINVAL, std::string(who) + ": bad format");
+  if (int rc = check_plain_args(dev, dev_out, out_bytes, true)) return rc;
+  if (dev->meshlet_count && !dev_kept_off) return fail(GTSR_EINVAL, std::string(who) + ": null kept offsets");
+  if (reinterpret_cast<uintptr_t>(dev_kept_off) & 3)
+    return fail(GTSR_EINVAL, std::string(who) + ": kept offsets must be 4-byte aligned");
+  if (format == GTSR_FORMAT_GTS && dev->bits_bytes % 8)
+    return fail(GTSR_EINVAL, std::string(who) + ": bits_bytes must be a multiple of 8");
+  Defaults d;
+  if (int rc = resolve_cfg(cfg, d, who)) return rc;
+  const uint32_t cus = cu_count();
+  if (!cus) return fail(GTSR_EHIP, std::string(who) + ": cannot query the device");
+  launch_plain(dev, dev_out, out_bytes, d, cus, static_cast<hipStream_t>(hip_stream), format == GTSR_FORMAT_GTS,
+               dev_kept_off);
+  return check_launch(who);
+}
+
+extern "C" int gtsr_decode_gts_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
+                                       const gtsr_work_item* dev_work, uint32_t work_items,
+                                       const gtsr_launch_cfg* cfg, void* hip_stream) {
+  return enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, cfg,
+                         static_cast<hipStream_t>(hip_stream), "gtsr_decode_gts_batched", true);
 }
 
 extern "C" int decode_meshlets_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,

@@ -31,6 +31,7 @@ struct gtsr_encoded {
   std::vector<uint8_t> reuse;
   std::vector<uint32_t> verts;
   std::vector<uint64_t> vert_off;
+  std::vector<uint32_t> kept_off;   // input triangles before each meshlet
   uint64_t input_triangles = 0, strip_triangles = 0, restarts = 0, reuse_count = 0;
   uint64_t split_meshlets = 0, payload_bits = 0, stored_bytes = 0;
 };
@@ -361,6 +362,7 @@ struct Piece {   // encoder output of a contiguous meshlet range
   std::vector<uint8_t> reuse;
   std::vector<uint32_t> verts;
   std::vector<uint32_t> vcount;
+  std::vector<uint32_t> kept;       // input triangles per meshlet
   uint64_t strip_tris = 0, restarts = 0, splits = 0, payload = 0, stored = 0;
 };
 
@@ -455,6 +457,7 @@ void emit_part(const uint32_t* idx, const Adjacency& A, const Stripper& st, size
   d.vert_count = static_cast<uint16_t>(V);
   P.desc.push_back(d);
   P.vcount.push_back(V);
+  P.kept.push_back(T - 4 * static_cast<uint32_t>(k1 - k0 - 1));
   const uint32_t n_ru = T + 2 - V;
   P.strip_tris += T;
   P.restarts += (k1 - k0) - 1;
@@ -518,6 +521,7 @@ extern "C" int encode_meshlets(const uint32_t* indices, uint64_t triangle_count,
   try {
     E->input_triangles = T;
     E->vert_off.push_back(0);
+    E->kept_off.push_back(0);
     if (T == 0) { *out = E; return ok(); }
     Adjacency A;
     build_adjacency(indices, T, vertex_count, A);
@@ -551,6 +555,8 @@ extern "C" int encode_meshlets(const uint32_t* indices, uint64_t triangle_count,
     E->reuse.reserve(n_reuse);
     E->verts.reserve(n_verts);
     E->vert_off.reserve(n_desc + 1);
+    E->kept_off.reserve(n_desc + 1);
+    uint64_t ko = 0;
     uint64_t chunk0 = 0, reuse0 = 0, out0 = 0, vo = 0;
     for (const Piece& P : pieces) {
       for (gtsr_meshlet d : P.desc) {
@@ -563,6 +569,7 @@ extern "C" int encode_meshlets(const uint32_t* indices, uint64_t triangle_count,
       E->reuse.insert(E->reuse.end(), P.reuse.begin(), P.reuse.end());
       E->verts.insert(E->verts.end(), P.verts.begin(), P.verts.end());
       for (uint32_t v : P.vcount) { vo += v; E->vert_off.push_back(vo); }
+      for (uint32_t k : P.kept) { ko += k; E->kept_off.push_back(static_cast<uint32_t>(ko)); }
       chunk0 += P.bits.size() / 2;
       reuse0 += P.reuse.size();
       out0 += P.strip_tris;
@@ -599,6 +606,7 @@ extern "C" int gtsr_encoded_view_get(const gtsr_encoded* e, gtsr_encoded_view* v
   v->vert_off = e->vert_off.data();
   v->payload_bits = e->payload_bits;
   v->stored_bytes = e->stored_bytes;
+  v->kept_off = e->kept_off.data();
   return ok();
 }
 

@@ -218,6 +218,115 @@ def test_autotune_picks_a_measured_shape_and_keeps_outputs():
         np.testing.assert_array_equal(pool.output(i).cpu().numpy(), ref)
 
 
+def gts_device(g):
+    up = lambda a: P.upload_padded(np.ascontiguousarray(a, np.uint8), "cuda")
+    return P.DeviceStream(up(g.desc), up(g.words), up(g.index), g.desc.size // 16, g.strip_triangles,
+                          format=P.FORMAT_GTS)
+
+
+def assert_gts_parity(g, cfgs, tag):
+    ref = O.decode_gts(g)
+    ds = gts_device(g)
+    for cfg in cfgs:
+        for fill in (0xAA, 0x55):
+            say(f"[gpu] plain GTS {tag} cfg={cfg} fill={fill:#x} tris={g.strip_triangles}")
+            out = torch.full((g.strip_triangles, 3), fill, dtype=torch.uint8, device="cuda")
+            P.decode(ds, out=out, cfg=cfg)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(out.cpu().numpy(), ref)
+
+
+def test_plain_gts_small_and_random_streams():
+    ms = [m for T in range(1, 7) for m in all_streams(T)]
+    rng = np.random.default_rng(99)
+    ms += [random_stream(rng, int(rng.integers(1, 257)), float(rng.uniform(0.05, 0.95))) for _ in range(2000)]
+    desc, bits, reuse, ts = pack(ms)
+    assert_gts_parity(O.gts_from_reuse(desc, bits, reuse, ts), CFGS, "streams")
+
+
+@pytest.mark.parametrize("caps", [(32, 64), (64, 126), (128, 256)])
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_plain_gts_encoded_meshes(name, caps):
+    m = MESHES[name]()
+    s = O.encode(m.tri, m.nverts, *caps)
+    g = O.gts_from_reuse(s.desc, s.bits, s.reuse, s.strip_triangles)
+    assert_gts_parity(g, CFGS[:3], f"{name} {caps}")
+    np.testing.assert_array_equal(O.decode_gts(g), O.decode(s))
+
+
+def test_plain_gts_batched():
+    libencs = [P.gts_from_reuse(P.encode(m.tri, m.nverts, *caps)) for m, caps in _batched_meshes()]
+    refs = [O.decode_gts(O.GtsStream(e.desc_bytes, e.bits, e.reuse, e.strip_triangles)) for e in libencs]
+    pool = P.Pool(libencs)
+    for target in (1, 700, 5000):
+        for cfg in (None, {"waves_per_group": 1, "groups_per_cu": 1}):
+            say(f"[gpu] plain GTS batched target={target} cfg={cfg}")
+            pool.plan(target)
+            pool.out.fill_(0xAA)
+            pool.decode_batched(cfg=cfg)
+            torch.cuda.synchronize()
+            for i, ref in enumerate(refs):
+                np.testing.assert_array_equal(pool.output(i).cpu().numpy(), ref)
+
+
+def assert_compact_parity(ds, full_ref, desc, cfgs, tag):
+    kept_ref, offs = O.compact(full_ref, desc)
+    for cfg in cfgs:
+        say(f"[gpu] compact {tag} format={ds.format} cfg={cfg} kept={kept_ref.shape[0]}")
+        out = torch.full((kept_ref.shape[0], 3), 0xAA, dtype=torch.uint8, device="cuda")
+        P.decode_compact(ds, offs.astype(np.uint32), out=out, cfg=cfg)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), kept_ref)
+
+
+def test_compact_streams_both_formats():
+    """Hand-packed streams, including reuse bytes that make degenerate
+    triangles outside restarts: every triple with a repeated index goes."""
+    ms = [m for T in range(1, 6) for m in all_streams(T)]
+    rng = np.random.default_rng(5)
+    ms += [random_stream(rng, int(rng.integers(1, 257)), float(rng.uniform(0.05, 0.95))) for _ in range(1500)]
+    desc, bits, reuse, ts = pack(ms)
+    full = O.decode_arrays(desc, bits, reuse, ts)
+    assert_compact_parity(device_stream(desc, bits, reuse, ts), full, desc, CFGS, "streams reuse")
+    g = O.gts_from_reuse(desc, bits, reuse, ts)
+    assert_compact_parity(gts_device(g), full, desc, CFGS[:2], "streams gts")
+
+
+@pytest.mark.parametrize("caps", [(32, 64), (64, 126), (128, 256)])
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_compact_encoded_meshes_both_formats(name, caps):
+    m = MESHES[name]()
+    sl = P.encode(m.tri, m.nverts, *caps)
+    full = O.decode_arrays(sl.desc_bytes, sl.bits, sl.reuse, sl.strip_triangles)
+    assert int(sl.kept_off[-1]) == m.ntri
+    ds = P.to_device(sl)
+    assert_compact_parity(ds, full, sl.desc_bytes, CFGS[:3], f"{name} {caps}")
+    out = P.decode_compact(ds, sl.kept_off)
+    torch.cuda.synchronize()
+    s = O.Stream(sl.desc_bytes, sl.bits, sl.reuse, sl.verts, sl.vert_off, sl.stats)
+    kept = out.cpu().numpy()
+    tri_meshlet = np.repeat(np.arange(sl.meshlet_count), np.diff(sl.kept_off.astype(np.int64)))
+    base = s.vert_off[:-1].astype(np.int64)[tri_meshlet]
+    np.testing.assert_array_equal(O.canonical(s.verts.astype(np.int64)[base[:, None] + kept.astype(np.int64)]),
+                                  O.canonical(m.tri))
+    assert_compact_parity(P.to_device(P.gts_from_reuse(sl)), full, sl.desc_bytes, CFGS[:1], f"{name} {caps}")
+
+
+def test_compact_output_too_small_skips_tail_meshlets():
+    m = meshgen.workload1()
+    sl = P.encode(m.tri, m.nverts, 64, 126)
+    full = O.decode_arrays(sl.desc_bytes, sl.bits, sl.reuse, sl.strip_triangles)
+    kept_ref, offs = O.compact(full, sl.desc_bytes)
+    cap = int(offs[len(offs) // 2]) + 5          # room for the first half and a few more
+    out = torch.full((cap, 3), 0xAA, dtype=torch.uint8, device="cuda")
+    P.decode_compact(P.to_device(sl), offs.astype(np.uint32), out=out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    h = int(offs[len(offs) // 2])
+    np.testing.assert_array_equal(got[:h], kept_ref[:h])
+    assert (got[h:] == 0xAA).all()
+
+
 def test_full_size_single_mesh():
     """The 5.2M-triangle icosphere (64v/126t caps) in the plain launch shape
     the benchmark uses: library stream == oracle stream, GPU decode == oracle

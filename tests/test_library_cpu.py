@@ -5,6 +5,7 @@ streams as the oracle encoder (both follow the same greedy rules); the
 library's stream validator must accept and reject exactly what the oracle's
 checker does.
 """
+import ctypes
 import os
 import re
 
@@ -181,3 +182,38 @@ def test_plan_batch():
             for (a, b), t in zip(zip(mine["first"], mine["end"]), tris):
                 assert t <= target or b - a == 1
     assert P.plan_batch([], 10).size == 0
+
+
+@pytest.mark.parametrize("caps", [(32, 64), (64, 126), (128, 256)])
+@pytest.mark.parametrize("name", ["grid64", "patch", "delaunay", "fan", "disjoint"])
+def test_library_gts_and_kept_offsets_equal_oracle(name, caps):
+    """Plain GTS re-encoding and kept offsets: library == oracle, byte for byte."""
+    m = MESHES[name]()
+    sl = P.encode(m.tri, m.nverts, *caps)
+    g = P.gts_from_reuse(sl)
+    go = O.gts_from_reuse(sl.desc_bytes, sl.bits, sl.reuse, sl.strip_triangles)
+    assert np.array_equal(g.desc_bytes, go.desc) and np.array_equal(g.bits, go.words)
+    assert np.array_equal(g.reuse, go.index)
+    _, offs = O.compact(O.decode(O.Stream(sl.desc_bytes, sl.bits, sl.reuse, sl.verts, sl.vert_off, sl.stats)),
+                        sl.desc_bytes)
+    np.testing.assert_array_equal(sl.kept_off.astype(np.uint64), offs)
+    assert int(sl.kept_off[-1]) == m.ntri
+    assert g.stats["stored_bytes"] == 16 * sl.meshlet_count + g.bits.size + g.reuse.size
+
+
+def test_gts_from_reuse_errors():
+    m = meshgen.workload1()
+    sl = P.encode(m.tri, m.nverts, 64, 126)
+    bad = P.Encoded(sl.meshlets.copy(), sl.bits.copy(), sl.reuse.copy(), sl.verts, sl.vert_off, sl.stats)
+    bad.bits[8] |= 1      # increment flag on triangle 0
+    with pytest.raises(P.GtsrError) as e:
+        P.gts_from_reuse(bad)
+    assert e.value.code == P.ECORRUPT
+    L = P.lib()
+    s = sl.host_stream()
+    gdesc = np.zeros(sl.meshlet_count, P.MESHLET_DTYPE)
+    words = np.zeros(sl.bits.size // 2, np.uint8)
+    index = np.zeros(sl.strip_triangles - sl.meshlet_count - 1, np.uint8)
+    rc = L.gtsr_gts_from_reuse(ctypes.byref(s), gdesc.ctypes.data, words.ctypes.data, words.size,
+                               index.ctypes.data, index.size)
+    assert rc == P.EINVAL
