@@ -160,6 +160,26 @@ def sphere(level: int, rng: np.random.Generator, permute: bool = True,
                 meta={"positions": pos, "level": level})
 
 
+def vertex_attributes(mesh: Mesh) -> np.ndarray:
+    """Eight float32 channels per vertex (position xyz, unit normal xyz,
+    texture uv) for meshes that carry positions: a sphere's jittered
+    positions with radial normals and spherical uv, or a Delaunay mesh's
+    points at z = 0 with normal +z and uv = xy."""
+    if "positions" in mesh.meta:
+        p = np.asarray(mesh.meta["positions"], np.float64)
+        nrm = p / np.linalg.norm(p, axis=1, keepdims=True)
+        uv = np.stack([np.arctan2(nrm[:, 1], nrm[:, 0]) / (2 * math.pi) + 0.5,
+                       np.arccos(np.clip(nrm[:, 2], -1.0, 1.0)) / math.pi], 1)
+    elif "points" in mesh.meta:
+        xy = np.asarray(mesh.meta["points"], np.float64)
+        p = np.concatenate([xy, np.zeros((xy.shape[0], 1))], 1)
+        nrm = np.tile([0.0, 0.0, 1.0], (xy.shape[0], 1))
+        uv = xy
+    else:
+        raise ValueError("mesh carries no positions")
+    return np.ascontiguousarray(np.concatenate([p, nrm, uv], 1), np.float32)
+
+
 def sphere_patch(n: int, rng: np.random.Generator, permute: bool = True) -> Mesh:
     """About ``n`` connected triangles cut from the smallest icosphere with at
     least ``n`` faces: the ``n`` faces whose centroids lie closest to a seeded

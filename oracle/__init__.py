@@ -30,7 +30,7 @@ def build() -> str:
     src = os.path.join(HERE, "oracle.c")
     tmp = LIB_PATH + ".tmp"
     subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
-                    "-o", tmp, src], check=True)
+                    "-o", tmp, src, "-lm"], check=True)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -73,6 +73,10 @@ def lib():
     L.oracle_gts_from_reuse.restype = C.c_int
     L.oracle_compact.argtypes = [vp, C.c_uint64, vp, C.c_uint64, u64p, vp, C.c_uint32, vp]
     L.oracle_compact.restype = C.c_int
+    L.oracle_quantize.argtypes = [vp, C.c_uint32, C.c_uint32, vp, vp, C.c_uint32, C.c_uint32, vp, vp, vp, vp]
+    L.oracle_quantize.restype = C.c_int
+    L.oracle_dequantize.argtypes = [vp, vp, vp, C.c_uint32, C.c_uint32, vp, vp, vp]
+    L.oracle_dequantize.restype = C.c_int
     _lib = L
     return L
 
@@ -230,6 +234,47 @@ def compact(decoded: np.ndarray, desc=None):
     if rc != OK:
         raise OracleError(rc)
     return out[:kept.value], offs
+
+
+@dataclass
+class Quantized:
+    """Crack-free fixed-point attributes: per channel origin and spacing,
+    per meshlet the lowest grid value, per meshlet-local vertex b-bit offsets."""
+
+    origin: np.ndarray   # float32[n]
+    delta: np.ndarray    # float32[n]
+    L: np.ndarray        # int32[M, n]
+    q: np.ndarray        # uint16[sum V, n]
+
+
+def quantize(attrs: np.ndarray, verts: np.ndarray, vert_off: np.ndarray, b: int = 16) -> Quantized:
+    L_ = lib()
+    attrs = np.ascontiguousarray(attrs, np.float32)
+    nv, n = attrs.shape
+    verts = np.ascontiguousarray(verts, np.uint32)
+    vert_off = np.ascontiguousarray(vert_off, np.uint64)
+    M = vert_off.size - 1
+    origin = np.zeros(n, np.float32)
+    delta = np.zeros(n, np.float32)
+    Lm = np.zeros((M, n), np.int32)
+    q = np.zeros((int(vert_off[-1]), n), np.uint16)
+    rc = L_.oracle_quantize(_ptr(attrs), nv, n, _ptr(verts), _ptr(vert_off), M, b, _ptr(origin), _ptr(delta),
+                            _ptr(Lm), _ptr(q))
+    if rc != OK:
+        raise OracleError(rc)
+    return Quantized(origin, delta, Lm, q)
+
+
+def dequantize(qz: Quantized, vert_off: np.ndarray) -> np.ndarray:
+    L_ = lib()
+    vert_off = np.ascontiguousarray(vert_off, np.uint64)
+    M, n = qz.L.shape
+    out = np.zeros(qz.q.shape, np.float32)
+    rc = L_.oracle_dequantize(_ptr(qz.L), _ptr(qz.q), _ptr(vert_off), M, n, _ptr(qz.origin), _ptr(qz.delta),
+                              _ptr(out))
+    if rc != OK:
+        raise OracleError(rc)
+    return out
 
 
 def check_stream(desc, bits, reuse, strip_triangles) -> int:

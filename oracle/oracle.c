@@ -47,6 +47,13 @@
  *                        Same sequential walk as oracle_decode.
  *   oracle_gts_from_reuse  Re-encodes a GTS-Reuse stream as plain GTS: walks
  *                        each meshlet's index stream and writes it out.
+ *   oracle_quantize      Sec. 4.4 "Crack-Free Fixed-Point Vertex Attribute
+ *   oracle_dequantize    Quantization": per channel, the largest meshlet extent
+ *                        w sets the global grid spacing w / (2^b - 1); every
+ *                        value is put on that grid, each meshlet stores its
+ *                        lowest grid value L and b-bit offsets from it;
+ *                        decoding adds L back and maps the grid value to
+ *                        floating point.
  *   oracle_compact       Drops the degenerate triangles of the restarts
  *                        (Sec. 4.2: four per restart; they are the only
  *                        triangles with a repeated index) from decoded
@@ -324,6 +331,100 @@ int oracle_compact(const uint8_t* tris, uint64_t n, uint8_t* out, uint64_t out_c
   while (desc && m < meshlet_count) offsets[m++] = k;
   if (desc) offsets[meshlet_count] = k;
   *kept = k;
+  return OR_OK;
+}
+
+/* ----------------------------------------------------- attribute quantization */
+
+#include <math.h>
+
+/*
+ * Crack-free fixed-point quantization (Sec. 4.4), channel by channel:
+ *   w      = largest extent (max - min) of the channel over any one meshlet;
+ *   delta  = w / (2^b - 1), taken as the smallest float32 not below it (1 if
+ *            w = 0), widened by 2^-20 relative steps while some meshlet's
+ *            grid values would still span more than 2^b - 1;
+ *   origin = the channel's minimum over all vertices (a float32 value);
+ *   G(v)   = floor((A(v) - origin) / delta), in float64: the vertex's value
+ *            on the global grid, the same in every meshlet that holds it;
+ *   L      = the lowest G in a meshlet; q = G - L in [0, 2^b - 1].
+ * Inputs: attrs float32[nverts][n]; the meshlets' local vertex lists
+ * verts[vert_off[m] .. vert_off[m+1]).  Outputs: origin[n], delta[n],
+ * L int32[M][n], q uint16[sum V][n] (b <= 16).  ELIMIT if a grid value does
+ * not fit 31 bits.
+ */
+int oracle_quantize(const float* attrs, uint32_t nverts, uint32_t n, const uint32_t* verts,
+                    const uint64_t* vert_off, uint32_t M, uint32_t b,
+                    float* origin, float* delta, int32_t* L, uint16_t* q) {
+  if (b < 1 || b > 16 || n == 0) return OR_EINVAL;
+  const double top = (double)((1u << b) - 1);
+  for (uint32_t i = 0; i < n; ++i) {
+    float lo = INFINITY;
+    for (uint32_t v = 0; v < nverts; ++v) if (attrs[(uint64_t)v * n + i] < lo) lo = attrs[(uint64_t)v * n + i];
+    if (nverts == 0) lo = 0.0f;
+    double w = 0.0;
+    for (uint32_t m = 0; m < M; ++m) {
+      float a = INFINITY, z = -INFINITY;
+      for (uint64_t k = vert_off[m]; k < vert_off[m + 1]; ++k) {
+        float x = attrs[(uint64_t)verts[k] * n + i];
+        if (x < a) a = x;
+        if (x > z) z = x;
+      }
+      if (vert_off[m + 1] > vert_off[m] && (double)z - (double)a > w) w = (double)z - (double)a;
+    }
+    float d = 1.0f;
+    if (w > 0.0) {
+      d = (float)(w / top);
+      if ((double)d < w / top) d = nextafterf(d, INFINITY);
+    }
+    for (;;) {
+      int fits = 1;
+      for (uint32_t m = 0; m < M && fits; ++m) {
+        double gmin = INFINITY, gmax = -INFINITY;
+        for (uint64_t k = vert_off[m]; k < vert_off[m + 1]; ++k) {
+          double g = floor(((double)attrs[(uint64_t)verts[k] * n + i] - (double)lo) / (double)d);
+          if (g < gmin) gmin = g;
+          if (g > gmax) gmax = g;
+        }
+        if (gmax >= 2147483647.0) return OR_ELIMIT;
+        if (vert_off[m + 1] > vert_off[m] && gmax - gmin > top) fits = 0;
+      }
+      if (fits) break;
+      d = (float)((double)d * (1.0 + 1.0 / 1048576.0));
+    }
+    origin[i] = lo;
+    delta[i] = d;
+    for (uint32_t m = 0; m < M; ++m) {
+      double gmin = INFINITY;
+      for (uint64_t k = vert_off[m]; k < vert_off[m + 1]; ++k) {
+        double g = floor(((double)attrs[(uint64_t)verts[k] * n + i] - (double)lo) / (double)d);
+        if (g < gmin) gmin = g;
+      }
+      int32_t Lm = vert_off[m + 1] > vert_off[m] ? (int32_t)gmin : 0;
+      L[(uint64_t)m * n + i] = Lm;
+      for (uint64_t k = vert_off[m]; k < vert_off[m + 1]; ++k) {
+        double g = floor(((double)attrs[(uint64_t)verts[k] * n + i] - (double)lo) / (double)d);
+        q[k * n + i] = (uint16_t)((int64_t)g - Lm);
+      }
+    }
+  }
+  return OR_OK;
+}
+
+/*
+ * Decode: the grid value L + q of every meshlet-local vertex, mapped back as
+ * (L + q) * delta + origin with one float64 fused multiply-add, rounded to
+ * float32 (a function of the grid value alone, so every copy of a vertex
+ * gets the same bits).  out float32[sum V][n].
+ */
+int oracle_dequantize(const int32_t* L, const uint16_t* q, const uint64_t* vert_off, uint32_t M, uint32_t n,
+                      const float* origin, const float* delta, float* out) {
+  for (uint32_t m = 0; m < M; ++m)
+    for (uint64_t k = vert_off[m]; k < vert_off[m + 1]; ++k)
+      for (uint32_t i = 0; i < n; ++i) {
+        int64_t g = (int64_t)L[(uint64_t)m * n + i] + q[k * n + i];
+        out[k * n + i] = (float)fma((double)g, (double)delta[i], (double)origin[i]);
+      }
   return OR_OK;
 }
 
