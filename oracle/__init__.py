@@ -73,6 +73,8 @@ def lib():
     L.oracle_gts_from_reuse.restype = C.c_int
     L.oracle_compact.argtypes = [vp, C.c_uint64, vp, C.c_uint64, u64p, vp, C.c_uint32, vp]
     L.oracle_compact.restype = C.c_int
+    L.oracle_min_strips.argtypes = [vp, C.c_uint32, u32p]
+    L.oracle_min_strips.restype = C.c_int
     L.oracle_quantize.argtypes = [vp, C.c_uint32, C.c_uint32, vp, vp, C.c_uint32, C.c_uint32, vp, vp, vp, vp]
     L.oracle_quantize.restype = C.c_int
     L.oracle_dequantize.argtypes = [vp, vp, vp, C.c_uint32, C.c_uint32, vp, vp, vp]
@@ -234,6 +236,17 @@ def compact(decoded: np.ndarray, desc=None):
     if rc != OK:
         raise OracleError(rc)
     return out[:kept.value], offs
+
+
+def min_strips(tri: np.ndarray) -> int:
+    """Fewest strips covering a tiny CCW triangle set (brute force, T <= 16)."""
+    L = lib()
+    tri = np.ascontiguousarray(tri, np.uint32).reshape(-1, 3)
+    out = C.c_uint32()
+    rc = L.oracle_min_strips(_ptr(tri), tri.shape[0], C.byref(out))
+    if rc != OK:
+        raise OracleError(rc)
+    return int(out.value)
 
 
 @dataclass

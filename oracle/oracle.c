@@ -54,6 +54,13 @@
  *                        lowest grid value L and b-bit offsets from it;
  *                        decoding adds L back and maps the grid value to
  *                        floating point.
+ *   oracle_min_strips    The fewest strips (restarts + 1) that cover a small
+ *                        triangle set (Sec. 3.1, the optimal GTS): any
+ *                        simple path of neighbouring triangles is a strip,
+ *                        so the answer is T minus the most neighbour pairs
+ *                        that can be chained with no triangle in three pairs
+ *                        (no fork) and no cycle; found by trying every subset
+ *                        of pairs (brute force, tiny inputs only).
  *   oracle_compact       Drops the degenerate triangles of the restarts
  *                        (Sec. 4.2: four per restart; they are the only
  *                        triangles with a repeated index) from decoded
@@ -501,6 +508,48 @@ static int build_adjacency(const uint32_t* tri, uint64_t T, int64_t* nbr, uint8_
     i = j;
   }
   free(he);
+  return OR_OK;
+}
+
+/*
+ * Brute-force optimum for tiny inputs (T <= 16, at most 24 neighbour pairs):
+ * every subset of neighbour pairs is tried; a subset is a set of strips when
+ * no triangle is in more than two of its pairs and it closes no cycle; the
+ * fewest strips is T minus the largest such subset.
+ */
+int oracle_min_strips(const uint32_t* tri, uint32_t T, uint32_t* min_strips) {
+  if (T > 16) return OR_ELIMIT;
+  if (T == 0) { *min_strips = 0; return OR_OK; }
+  int64_t nbr[48];
+  uint8_t nbr_edge[48];
+  int rc = build_adjacency(tri, T, nbr, nbr_edge);
+  if (rc != OR_OK) return rc;
+  uint32_t ea[24], eb[24], E = 0;
+  for (uint32_t t = 0; t < T; ++t)
+    for (int e = 0; e < 3; ++e)
+      if (nbr[3 * t + e] > (int64_t)t) {
+        if (E == 24) return OR_ELIMIT;
+        ea[E] = t; eb[E] = (uint32_t)nbr[3 * t + e]; ++E;
+      }
+  uint32_t best = 0;
+  for (uint32_t mask = 0; mask < (1u << E); ++mask) {
+    uint32_t cnt = (uint32_t)__builtin_popcount(mask);
+    if (cnt <= best) continue;
+    uint32_t deg[16] = {0}, parent[16];
+    for (uint32_t t = 0; t < T; ++t) parent[t] = t;
+    int ok = 1;
+    for (uint32_t k = 0; k < E && ok; ++k) {
+      if (!(mask >> k & 1u)) continue;
+      if (++deg[ea[k]] > 2 || ++deg[eb[k]] > 2) { ok = 0; break; }
+      uint32_t a = ea[k], b = eb[k];
+      while (parent[a] != a) a = parent[a];
+      while (parent[b] != b) b = parent[b];
+      if (a == b) ok = 0;          /* would close a cycle */
+      else parent[a] = b;
+    }
+    if (ok) best = cnt;
+  }
+  *min_strips = T - best;
   return OR_OK;
 }
 
