@@ -74,11 +74,21 @@ typedef struct gtsr_meshlet {
   uint16_t vert_count;
 } gtsr_meshlet;
 
+/* gtsr_encode_params.flags */
+enum {
+  /* After the greedy strips of a meshlet, search for fewer strips (the
+   * optimal GTS of Sec. 3.1; the paper solves a MILP): branch and bound over
+   * chains of neighbouring triangles, 200000 search nodes per meshlet, kept
+   * when it beats the greedy count.  Streams then differ from the greedy
+   * encoder's; decoding is unchanged. */
+  GTSR_ENCODE_EXACT_STRIPS = 1
+};
+
 typedef struct gtsr_encode_params {
   uint32_t max_vertices;    /* 3..256 */
   uint32_t max_triangles;   /* 1..256; bounds T_s (restart degenerates count) */
   uint32_t threads;         /* 0 = all hardware threads */
-  uint32_t reserved;        /* must be 0 */
+  uint32_t flags;           /* GTSR_ENCODE_* bits; others must be 0 */
 } gtsr_encode_params;
 
 typedef struct gtsr_encoded gtsr_encoded;   /* opaque, host memory, library-owned */
@@ -104,6 +114,8 @@ typedef struct gtsr_encoded_view {
   const uint32_t* kept_off;     /* meshlet_count + 1 entries: input triangles before meshlet m
                                    (strip triangles minus restart degenerates); the offsets of a
                                    compacted output (gtsr_decode_compact) */
+  uint64_t exact_tried;         /* GTSR_ENCODE_EXACT_STRIPS: meshlets searched */
+  uint64_t exact_proven;        /* ... of which the search finished (optimal strips) */
 } gtsr_encoded_view;
 
 /* One encoded mesh.  For decode_meshlets the three pointers are device
@@ -162,6 +174,16 @@ typedef struct gtsr_work_item {
  * ENOMEM. */
 int encode_meshlets(const uint32_t* indices, uint64_t triangle_count, uint32_t vertex_count,
                     const gtsr_encode_params* params, gtsr_encoded** out);
+
+/* Fewest strips that cover a triangle set of at most 256 CCW triangles (the
+ * optimal GTS of Sec. 3.1), by the branch and bound of
+ * GTSR_ENCODE_EXACT_STRIPS from no incumbent, stopped after node_limit
+ * search nodes: *strips gets the best count found, *proven 1 if the search
+ * finished (the count is optimal).  Neighbours are as for the encoder
+ * (edges shared by exactly two triangles in opposite directions).  Errors:
+ * EINVAL, ELIMIT (more than 256 triangles), ENOMEM. */
+int gtsr_min_strips(const uint32_t* indices, uint32_t triangle_count, uint64_t node_limit, uint32_t* strips,
+                    uint32_t* proven);
 
 /* Fill *view with pointers into e.  Errors: EINVAL on null. */
 int gtsr_encoded_view_get(const gtsr_encoded* e, gtsr_encoded_view* view);
@@ -385,6 +407,46 @@ int gtsr_server_replay(gtsr_server* server, const uint64_t* arrival_ns, const ui
 /* Stop the scheduler, wait for batches on the device, free everything the
  * server allocated (not the arena). */
 void gtsr_server_destroy(gtsr_server* server);
+
+/* ------------------------------------------------- vertex attributes */
+
+/* Crack-free fixed-point quantization of per-vertex attributes (Sec. 4.4),
+ * host side.  attrs: float32[vertex_count][channels]; the meshlets' vertex
+ * lists verts[vert_off[m] .. vert_off[m+1]) (gtsr_encoded_view).  Per channel
+ * the global grid spacing is w / (2^bits - 1), w the widest meshlet extent,
+ * kept as the smallest float32 not below it (1 for a flat channel, widened
+ * in 2^-20 relative steps if float64 rounding would let a meshlet span more
+ * than 2^bits - 1 steps); origin = the channel minimum; a value's grid index
+ * is floor((A - origin) / delta) in float64.  Outputs (caller-owned, host):
+ * origin[channels], delta[channels], lowest int32[meshlet_count][channels]
+ * (each meshlet's lowest grid value), offsets uint16[vert_off[M]][channels]
+ * (grid value - lowest).  Errors: EINVAL (bits not 1..16, channels not
+ * 1..64, null pointer, bad ids), ELIMIT (a grid value past 31 bits). */
+int gtsr_quantize_attributes(const float* attrs, uint32_t vertex_count, uint32_t channels, const uint32_t* verts,
+                             const uint64_t* vert_off, uint32_t meshlet_count, uint32_t bits, float* origin,
+                             float* delta, int32_t* lowest, uint16_t* offsets);
+
+/* Quantized attributes in device memory (gtsr_quantize_attributes' outputs
+ * and the meshlets' vert_off, uint64[meshlet_count + 1]). */
+typedef struct gtsr_attr_stream {
+  const int32_t* lowest;
+  const uint16_t* offsets;
+  const uint64_t* vert_off;
+  const float* origin;
+  const float* delta;
+  uint32_t meshlet_count;
+  uint32_t channels;          /* 1..64 */
+} gtsr_attr_stream;
+
+/* Dequantize on the GPU: dev_out float32[vert_off[M]][channels] receives
+ * (lowest + offset) * delta + origin per meshlet-local vertex and channel,
+ * computed as one float64 fused multiply-add rounded to float32, so copies of
+ * a vertex in different meshlets get identical bits.  out_count: elements the
+ * output holds; meshlets whose range passes it are skipped.  cfg (may be
+ * NULL): waves_per_group 1..4, meshlets_per_wave.  Enqueued on hip_stream,
+ * allocates nothing.  Errors: EINVAL, EHIP. */
+int gtsr_dequantize(const gtsr_attr_stream* dev, float* dev_out, uint64_t out_count, const gtsr_launch_cfg* cfg,
+                    void* hip_stream);
 
 /* Enqueue a captured graph on hip_stream.  Errors: EINVAL, EHIP. */
 int gtsr_graph_launch(void* graph_exec, void* hip_stream);

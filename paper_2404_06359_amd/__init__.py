@@ -28,6 +28,7 @@ EXPORTED = (
     "gtsr_server_create", "gtsr_server_submit", "gtsr_server_poll", "gtsr_server_release",
     "gtsr_server_get_stats", "gtsr_server_replay", "gtsr_server_destroy",
     "gtsr_gts_from_reuse", "gtsr_decode_gts", "gtsr_decode_gts_batched", "gtsr_decode_compact",
+    "gtsr_quantize_attributes", "gtsr_dequantize", "gtsr_min_strips",
 )
 
 
@@ -42,9 +43,12 @@ class Meshlet(C.Structure):
                 ("tri_count", C.c_uint16), ("vert_count", C.c_uint16)]
 
 
+ENCODE_EXACT_STRIPS = 1
+
+
 class EncodeParams(C.Structure):
     _fields_ = [("max_vertices", C.c_uint32), ("max_triangles", C.c_uint32),
-                ("threads", C.c_uint32), ("reserved", C.c_uint32)]
+                ("threads", C.c_uint32), ("flags", C.c_uint32)]
 
 
 class EncodedView(C.Structure):
@@ -54,7 +58,8 @@ class EncodedView(C.Structure):
                 ("meshlets", C.c_void_p), ("bits", C.c_void_p), ("bits_bytes", C.c_uint64),
                 ("reuse", C.c_void_p), ("reuse_bytes", C.c_uint64),
                 ("vertices", C.c_void_p), ("vert_off", C.c_void_p),
-                ("payload_bits", C.c_uint64), ("stored_bytes", C.c_uint64), ("kept_off", C.c_void_p)]
+                ("payload_bits", C.c_uint64), ("stored_bytes", C.c_uint64), ("kept_off", C.c_void_p),
+                ("exact_tried", C.c_uint64), ("exact_proven", C.c_uint64)]
 
 
 class StreamDesc(C.Structure):
@@ -77,6 +82,12 @@ class TunePoint(C.Structure):
         return {"target_tris": self.target_tris, "work_items": self.work_items,
                 "waves_per_group": self.cfg.waves_per_group, "groups_per_cu": self.cfg.groups_per_cu,
                 "median_ms": self.median_ms, "min_ms": self.min_ms}
+
+
+class AttrStream(C.Structure):
+    _fields_ = [("lowest", C.c_void_p), ("offsets", C.c_void_p), ("vert_off", C.c_void_p),
+                ("origin", C.c_void_p), ("delta", C.c_void_p), ("meshlet_count", C.c_uint32),
+                ("channels", C.c_uint32)]
 
 
 class ServerParams(C.Structure):
@@ -144,6 +155,9 @@ def lib():
         "gtsr_decode_gts": (C.c_int, [C.POINTER(StreamDesc), vp, u64, C.POINTER(LaunchCfg), vp]),
         "gtsr_decode_gts_batched": (C.c_int, [vp, u32, vp, u32, C.POINTER(LaunchCfg), vp]),
         "gtsr_decode_compact": (C.c_int, [C.POINTER(StreamDesc), u32, vp, vp, u64, C.POINTER(LaunchCfg), vp]),
+        "gtsr_quantize_attributes": (C.c_int, [vp, u32, u32, vp, vp, u32, u32, vp, vp, vp, vp]),
+        "gtsr_dequantize": (C.c_int, [C.POINTER(AttrStream), vp, u64, C.POINTER(LaunchCfg), vp]),
+        "gtsr_min_strips": (C.c_int, [vp, u32, u64, C.POINTER(u32), C.POINTER(u32)]),
     }
     for name, (rt, args) in sig.items():
         f = getattr(L, name)
@@ -204,11 +218,13 @@ class Encoded:
 
 
 def encode(tri: np.ndarray, nverts: int, max_vertices: int = 64, max_triangles: int = 126,
-           threads: int = 0) -> Encoded:
-    """Encode a CCW triangle list (``uint32[T,3]``) with the library encoder."""
+           threads: int = 0, exact_strips: bool = False) -> Encoded:
+    """Encode a CCW triangle list (``uint32[T,3]``) with the library encoder;
+    ``exact_strips`` searches each meshlet for fewer strips than the greedy
+    rule finds (``GTSR_ENCODE_EXACT_STRIPS``)."""
     L = lib()
     tri = np.ascontiguousarray(tri, dtype=np.uint32).reshape(-1, 3)
-    params = EncodeParams(max_vertices, max_triangles, threads, 0)
+    params = EncodeParams(max_vertices, max_triangles, threads, ENCODE_EXACT_STRIPS if exact_strips else 0)
     h = C.c_void_p()
     _check(L.encode_meshlets(tri.ctypes.data if tri.size else None, tri.shape[0], nverts,
                              C.byref(params), C.byref(h)))
@@ -231,10 +247,21 @@ def encode(tri: np.ndarray, nverts: int, max_vertices: int = 64, max_triangles: 
         stats = {k: int(getattr(v, k)) for k in ("input_triangles", "strip_triangles", "restarts",
                                                  "reuse_count", "split_meshlets", "payload_bits",
                                                  "stored_bytes")}
+        if exact_strips:
+            stats["exact_tried"], stats["exact_proven"] = int(v.exact_tried), int(v.exact_proven)
         kept_off = take(v.kept_off, M + 1, np.uint32)
     finally:
         L.gtsr_encoded_free(h)
     return Encoded(meshlets, bits, reuse, verts, vert_off, stats, kept_off)
+
+
+def min_strips(tri: np.ndarray, node_limit: int = 1_000_000):
+    """``gtsr_min_strips``: (fewest strips found, whether proven optimal)."""
+    tri = np.ascontiguousarray(tri, dtype=np.uint32).reshape(-1, 3)
+    s, p = C.c_uint32(), C.c_uint32()
+    _check(lib().gtsr_min_strips(tri.ctypes.data if tri.size else None, tri.shape[0], node_limit, C.byref(s),
+                                 C.byref(p)))
+    return int(s.value), bool(p.value)
 
 
 def gts_from_reuse(enc: Encoded) -> Encoded:
@@ -653,3 +680,72 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------- vertex attributes
+
+@dataclass
+class QuantizedAttrs:
+    """Crack-free fixed-point attributes of one encoded mesh (host arrays)."""
+
+    origin: np.ndarray    # float32[n]
+    delta: np.ndarray     # float32[n]
+    lowest: np.ndarray    # int32[M, n]
+    offsets: np.ndarray   # uint16[sum V, n]
+    vert_off: np.ndarray  # uint64[M + 1]
+
+
+def quantize_attributes(attrs: np.ndarray, enc: Encoded, bits: int = 16) -> QuantizedAttrs:
+    """``gtsr_quantize_attributes`` over the meshlets of ``enc``;
+    ``attrs``: float32[vertex_count, channels]."""
+    attrs = np.ascontiguousarray(attrs, np.float32)
+    nv, n = attrs.shape
+    M = enc.meshlet_count
+    vert_off = np.ascontiguousarray(enc.vert_off, np.uint64)
+    verts = np.ascontiguousarray(enc.verts, np.uint32)
+    origin = np.zeros(n, np.float32)
+    delta = np.zeros(n, np.float32)
+    lowest = np.zeros((M, n), np.int32)
+    offsets = np.zeros((int(vert_off[-1]) if M else 0, n), np.uint16)
+    ptr = lambda a: a.ctypes.data if a.size else None
+    _check(lib().gtsr_quantize_attributes(ptr(attrs), nv, n, ptr(verts), ptr(vert_off), M, bits, ptr(origin),
+                                          ptr(delta), ptr(lowest), ptr(offsets)))
+    return QuantizedAttrs(origin, delta, lowest, offsets, vert_off)
+
+
+@dataclass
+class DeviceAttrs:
+    """``QuantizedAttrs`` resident on the device (torch tensors)."""
+
+    lowest: object
+    offsets: object
+    vert_off: object
+    origin: object
+    delta: object
+    meshlet_count: int
+    channels: int
+
+    def desc(self) -> AttrStream:
+        return AttrStream(self.lowest.data_ptr(), self.offsets.data_ptr(), self.vert_off.data_ptr(),
+                          self.origin.data_ptr(), self.delta.data_ptr(), self.meshlet_count, self.channels)
+
+    @property
+    def elements(self) -> int:
+        return self.offsets.numel() // 2
+
+
+def attrs_to_device(q: QuantizedAttrs, device="cuda") -> DeviceAttrs:
+    up = lambda a: upload_padded(np.ascontiguousarray(a), device)
+    return DeviceAttrs(up(q.lowest), up(q.offsets), up(q.vert_off), up(q.origin), up(q.delta),
+                       int(q.lowest.shape[0]), int(q.origin.shape[0]))
+
+
+def dequantize(da: DeviceAttrs, out=None, stream=None, cfg=None):
+    """``gtsr_dequantize``: float32[sum V, channels] on the device."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((da.elements // max(da.channels, 1), da.channels), dtype=torch.float32,
+                          device=da.offsets.device)
+    d = da.desc()
+    _check(lib().gtsr_dequantize(C.byref(d), out.data_ptr(), out.numel(), _cfg(cfg), _stream_handle(stream)))
+    return out

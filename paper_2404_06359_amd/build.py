@@ -21,8 +21,8 @@ ARCH = os.environ.get("GTSR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")
 
-HOST_SOURCES = ["encode.cpp", "capi.cpp", "tune.cpp", "serve.cpp"]
-HIP_SOURCES = ["decode.hip"]
+HOST_SOURCES = ["encode.cpp", "capi.cpp", "tune.cpp", "serve.cpp", "quant.cpp"]
+HIP_SOURCES = ["decode.hip", "attrs.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]
 # Host files that call the HIP runtime API (autotuner, server) compile with g++.

@@ -34,6 +34,7 @@ struct gtsr_encoded {
   std::vector<uint32_t> kept_off;   // input triangles before each meshlet
   uint64_t input_triangles = 0, strip_triangles = 0, restarts = 0, reuse_count = 0;
   uint64_t split_meshlets = 0, payload_bits = 0, stored_bytes = 0;
+  uint64_t exact_tried = 0, exact_proven = 0;
 };
 
 namespace gtsr {
@@ -288,6 +289,36 @@ class Stripper {
   uint8_t path_exit[kMaxStripTris];
   uint32_t path_len = 0;
 
+  const int16_t* local_nbrs() const { return lnbr_; }
+  uint32_t size() const { return n_; }
+  // Replaces the strips by the paths given as per-triangle chosen links
+  // (link[3p+e]: the pair across edge e of position p is chained): a path
+  // starts at its lowest-positioned end, paths in order of that position.
+  void set_paths(const uint8_t* link, const uint32_t* mt) {
+    strips.clear();
+    path_len = 0;
+    for (uint32_t i = 0; i < n_; ++i) used_[i] = 0;
+    for (uint32_t i = 0; i < n_; ++i) {
+      if (used_[i]) continue;
+      uint32_t d = link[3 * i] + link[3 * i + 1] + link[3 * i + 2];
+      if (d > 1) continue;   // not an end: reached from one
+      Strip st{path_len, 0};
+      int cur = static_cast<int>(i), prev = -1;
+      for (;;) {
+        used_[cur] = 1;
+        int next = -1, ne = 0;
+        for (int e = 0; e < 3; ++e)
+          if (link[3 * cur + e] && lnbr_[3 * cur + e] != prev) { next = lnbr_[3 * cur + e]; ne = e; }
+        push(mt[cur], static_cast<uint8_t>(next >= 0 ? ne : 0));
+        ++st.len;
+        if (next < 0) break;
+        prev = cur;
+        cur = next;
+      }
+      strips.push_back(st);
+    }
+  }
+
  private:
   uint32_t free_nbrs(int p) const {
     uint32_t c = 0;
@@ -364,6 +395,7 @@ struct Piece {   // encoder output of a contiguous meshlet range
   std::vector<uint32_t> vcount;
   std::vector<uint32_t> kept;       // input triangles per meshlet
   uint64_t strip_tris = 0, restarts = 0, splits = 0, payload = 0, stored = 0;
+  uint64_t exact_tried = 0, exact_proven = 0;
 };
 
 // Small map from global vertex number to local id for one meshlet part.
@@ -465,14 +497,121 @@ void emit_part(const uint32_t* idx, const Adjacency& A, const Stripper& st, size
   P.stored += 16 + 16ull * nch + n_ru;
 }
 
+// ------------------------------------------------------------ exact strips
+
+// Fewest strips over one triangle set by branch and bound (the optimal GTS of
+// Sec. 3.1, which the paper finds with a MILP).  Any simple path of
+// neighbouring triangles is a strip, so the task is to chain as many
+// neighbour pairs as possible such that no triangle is in more than two
+// chained pairs (no fork) and no chained pairs close a cycle; strips = n -
+// chained.  Depth-first over the pairs in order (include before exclude),
+// with the bound chained + floor(sum over triangles of min(2 - degree,
+// undecided pairs at it) / 2), and an incumbent to beat.  Stops after
+// node_limit nodes; `proven` tells whether the search space was exhausted.
+class ExactStrips {
+ public:
+  uint32_t solve(const int16_t* lnbr, uint32_t n, uint32_t incumbent_strips, uint64_t node_limit, bool* proven) {
+    n_ = n;
+    pa_.clear(); pb_.clear(); ea_.clear(); eb_.clear();
+    for (uint32_t t = 0; t < n; ++t)
+      for (int e = 0; e < 3; ++e) {
+        const int q = lnbr[3 * t + e];
+        if (q > static_cast<int>(t)) {
+          int eq = 0;
+          for (int f = 0; f < 3; ++f) if (lnbr[3 * q + f] == static_cast<int>(t)) eq = f;
+          pa_.push_back(t); pb_.push_back(static_cast<uint32_t>(q)); ea_.push_back(e); eb_.push_back(eq);
+        }
+      }
+    const size_t E = pa_.size();
+    deg_.assign(n, 0); und_.assign(n, 0); parent_.resize(n); chosen_.assign(E, 0);
+    for (uint32_t t = 0; t < n; ++t) parent_[t] = t;
+    for (size_t k = 0; k < E; ++k) { ++und_[pa_[k]]; ++und_[pb_[k]]; }
+    pot_ = 0;
+    for (uint32_t t = 0; t < n; ++t) pot_ += contrib(t);
+    best_ = n >= incumbent_strips ? n - incumbent_strips : 0;   // chained pairs to beat
+    have_best_ = false;
+    nodes_ = 0; limit_ = node_limit; aborted_ = false;
+    dfs(0, 0);
+    *proven = !aborted_;
+    return n - best_;
+  }
+  bool improved() const { return have_best_; }
+  // per-triangle chained links of the best solution (valid when improved())
+  void links(uint8_t* link) const {
+    std::memset(link, 0, 3 * n_);
+    for (size_t k = 0; k < pa_.size(); ++k)
+      if (best_sel_[k]) { link[3 * pa_[k] + ea_[k]] = 1; link[3 * pb_[k] + eb_[k]] = 1; }
+  }
+
+ private:
+  uint32_t contrib(uint32_t t) const { return std::min<uint32_t>(2 - deg_[t], und_[t]); }
+  uint32_t find(uint32_t x) const { while (parent_[x] != x) x = parent_[x]; return x; }
+  void dfs(size_t k, uint32_t chained) {
+    if (aborted_) return;
+    if (++nodes_ > limit_) { aborted_ = true; return; }
+    if (chained > best_) {
+      best_ = chained;
+      best_sel_ = chosen_;
+      have_best_ = true;
+    }
+    if (k == pa_.size() || chained + pot_ / 2 <= best_) return;
+    const uint32_t a = pa_[k], b = pb_[k];
+    const uint32_t before = contrib(a) + contrib(b);
+    --und_[a]; --und_[b];
+    // include
+    if (deg_[a] < 2 && deg_[b] < 2) {
+      const uint32_t ra = find(a), rb = find(b);
+      if (ra != rb) {
+        ++deg_[a]; ++deg_[b];
+        parent_[ra] = rb;
+        chosen_[k] = 1;
+        pot_ = pot_ - before + contrib(a) + contrib(b);
+        dfs(k + 1, chained + 1);
+        pot_ = pot_ - contrib(a) - contrib(b) + before;
+        chosen_[k] = 0;
+        parent_[ra] = ra;
+        --deg_[a]; --deg_[b];
+      }
+    }
+    // exclude
+    pot_ = pot_ - before + contrib(a) + contrib(b);
+    dfs(k + 1, chained);
+    pot_ = pot_ - contrib(a) - contrib(b) + before;
+    ++und_[a]; ++und_[b];
+  }
+
+  uint32_t n_ = 0;
+  std::vector<uint32_t> pa_, pb_;
+  std::vector<int> ea_, eb_;
+  std::vector<uint32_t> deg_, und_, parent_;
+  std::vector<uint8_t> chosen_, best_sel_;
+  uint64_t pot_ = 0, nodes_ = 0, limit_ = 0;
+  uint32_t best_ = 0;
+  bool have_best_ = false, aborted_ = false;
+};
+
+constexpr uint64_t kExactNodeLimit = 200000;   // search nodes per meshlet
+
 void encode_range(const uint32_t* idx, const Adjacency& A, const Meshlets& M, uint32_t m0, uint32_t m1,
-                  uint32_t max_t, Piece& P) {
+                  uint32_t max_t, bool exact, Piece& P) {
   Stripper* st = new Stripper();
   LocalIds* ids = new LocalIds();
+  ExactStrips* ex = exact ? new ExactStrips() : nullptr;
+  uint8_t link[3 * kMaxStripTris];
   for (uint32_t m = m0; m < m1; ++m) {
     const uint32_t* mt = M.tris.data() + M.start[m];
     const uint32_t n = M.start[m + 1] - M.start[m];
     st->run(mt, n, m, A, M);
+    if (ex && st->strips.size() > 1) {
+      bool proven = false;
+      ex->solve(st->local_nbrs(), n, static_cast<uint32_t>(st->strips.size()), kExactNodeLimit, &proven);
+      if (ex->improved()) {
+        ex->links(link);
+        st->set_paths(link, mt);
+      }
+      P.exact_proven += proven;
+      P.exact_tried += 1;
+    }
     // pack strips, in order, into parts of at most max_t strip triangles
     size_t k = 0;
     bool first = true;
@@ -491,6 +630,7 @@ void encode_range(const uint32_t* idx, const Adjacency& A, const Meshlets& M, ui
   }
   delete st;
   delete ids;
+  delete ex;
 }
 
 }  // namespace
@@ -504,8 +644,11 @@ extern "C" int encode_meshlets(const uint32_t* indices, uint64_t triangle_count,
   *out = nullptr;
   if (!indices && triangle_count) return fail(GTSR_EINVAL, "encode_meshlets: null indices");
   const uint32_t max_v = params->max_vertices, max_t = params->max_triangles;
-  if (max_v < 3 || max_v > 256 || max_t < 1 || max_t > 256 || params->reserved)
+  if (max_v < 3 || max_v > 256 || max_t < 1 || max_t > 256)
     return fail(GTSR_ELIMIT, "encode_meshlets: max_vertices must be 3..256, max_triangles 1..256");
+  if (params->flags & ~uint32_t(GTSR_ENCODE_EXACT_STRIPS))
+    return fail(GTSR_EINVAL, "encode_meshlets: unknown flags");
+  const bool exact = params->flags & GTSR_ENCODE_EXACT_STRIPS;
   if (triangle_count > 0xFFFFFFFFull / 5)
     return fail(GTSR_ELIMIT, "encode_meshlets: too many triangles for 32-bit offsets");
   const uint32_t T = static_cast<uint32_t>(triangle_count);
@@ -536,8 +679,9 @@ extern "C" int encode_meshlets(const uint32_t* indices, uint64_t triangle_count,
     for (uint32_t i = 0; i < threads; ++i) {
       uint32_t m0 = static_cast<uint32_t>(uint64_t(nm) * i / threads);
       uint32_t m1 = static_cast<uint32_t>(uint64_t(nm) * (i + 1) / threads);
-      if (threads == 1) encode_range(indices, A, M, m0, m1, max_t, pieces[i]);
-      else pool.emplace_back(encode_range, indices, std::cref(A), std::cref(M), m0, m1, max_t, std::ref(pieces[i]));
+      if (threads == 1) encode_range(indices, A, M, m0, m1, max_t, exact, pieces[i]);
+      else pool.emplace_back(encode_range, indices, std::cref(A), std::cref(M), m0, m1, max_t, exact,
+                             std::ref(pieces[i]));
     }
     for (auto& th : pool) th.join();
 
@@ -577,6 +721,8 @@ extern "C" int encode_meshlets(const uint32_t* indices, uint64_t triangle_count,
       E->split_meshlets += P.splits;
       E->payload_bits += P.payload;
       E->stored_bytes += P.stored;
+      E->exact_tried += P.exact_tried;
+      E->exact_proven += P.exact_proven;
     }
     E->strip_triangles = out0;
     E->reuse_count = reuse0;
@@ -607,7 +753,31 @@ extern "C" int gtsr_encoded_view_get(const gtsr_encoded* e, gtsr_encoded_view* v
   v->payload_bits = e->payload_bits;
   v->stored_bytes = e->stored_bytes;
   v->kept_off = e->kept_off.data();
+  v->exact_tried = e->exact_tried;
+  v->exact_proven = e->exact_proven;
   return ok();
 }
 
 extern "C" void gtsr_encoded_free(gtsr_encoded* e) { delete e; }
+
+extern "C" int gtsr_min_strips(const uint32_t* indices, uint32_t triangle_count, uint64_t node_limit,
+                               uint32_t* strips, uint32_t* proven) {
+  if (!strips || !proven || (triangle_count && !indices)) return fail(GTSR_EINVAL, "gtsr_min_strips: null argument");
+  if (triangle_count > kMaxStripTris) return fail(GTSR_ELIMIT, "gtsr_min_strips: more than 256 triangles");
+  uint32_t V = 0;
+  for (uint64_t k = 0; k < 3ull * triangle_count; ++k) V = std::max(V, indices[k] + 1);
+  try {
+    Adjacency A;
+    build_adjacency(indices, triangle_count, V, A);
+    int16_t lnbr[3 * kMaxStripTris];
+    for (uint64_t h = 0; h < 3ull * triangle_count; ++h)
+      lnbr[h] = A.nbr[h] == kNone ? int16_t(-1) : static_cast<int16_t>(A.nbr[h]);
+    ExactStrips ex;
+    bool done = false;
+    *strips = triangle_count ? ex.solve(lnbr, triangle_count, triangle_count, node_limit, &done) : 0;
+    *proven = done ? 1u : 0u;
+  } catch (const std::bad_alloc&) {
+    return fail(GTSR_ENOMEM, "gtsr_min_strips: out of memory");
+  }
+  return ok();
+}

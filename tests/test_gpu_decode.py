@@ -114,6 +114,19 @@ def test_encoded_meshes(name, caps):
     assert_parity(s.desc, s.bits, s.reuse, s.strip_triangles, CFGS[:3], f"{name} {caps}")
 
 
+@pytest.mark.parametrize("caps", [(32, 64), (128, 256)])
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_exact_strip_streams(name, caps):
+    """Streams from the exact stripifier (fewer restarts, different strips):
+    GPU decode == oracle decode, and the round trip restores the mesh."""
+    m = MESHES[name]()
+    e = P.encode(m.tri, m.nverts, *caps, exact_strips=True)
+    assert_parity(e.desc_bytes, e.bits, e.reuse, e.strip_triangles, CFGS[:2], f"exact {name} {caps}")
+    got = P.decode(P.to_device(e)).cpu().numpy()
+    s = O.Stream(e.desc_bytes, e.bits, e.reuse, e.verts, e.vert_off, e.stats)
+    np.testing.assert_array_equal(O.round_trip_triangles(s, got), O.canonical(m.tri))
+
+
 def test_library_stream_equals_oracle_stream_and_decodes():
     m = meshgen.workload1()
     so = O.encode(m.tri, m.nverts, 64, 126)

@@ -57,7 +57,7 @@ def test_struct_layouts_match_header(tmp_path):
         "gtsr_stream": P.StreamDesc, "gtsr_launch_cfg": P.LaunchCfg, "gtsr_tune_point": P.TunePoint,
         "gtsr_server_params": P.ServerParams, "gtsr_server_stats": P.ServerStats,
         "gtsr_mesh_entry": P.MESH_ENTRY_DTYPE, "gtsr_work_item": P.WORK_ITEM_DTYPE,
-        "gtsr_completion": P.COMPLETION_DTYPE,
+        "gtsr_completion": P.COMPLETION_DTYPE, "gtsr_attr_stream": P.AttrStream,
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gtsr.h"', "int main(void) {"]
     want = []
@@ -217,3 +217,54 @@ def test_gts_from_reuse_errors():
     rc = L.gtsr_gts_from_reuse(ctypes.byref(s), gdesc.ctypes.data, words.ctypes.data, words.size,
                                index.ctypes.data, index.size)
     assert rc == P.EINVAL
+
+
+@pytest.mark.parametrize("bits", [16, 10])
+@pytest.mark.parametrize("caps", [(32, 64), (128, 256)])
+@pytest.mark.parametrize("name", ["sphere5", "delaunay"])
+def test_library_quantization_equals_oracle(name, caps, bits):
+    m = MESHES[name]()
+    A = meshgen.vertex_attributes(m)
+    sl = P.encode(m.tri, m.nverts, *caps)
+    ql = P.quantize_attributes(A, sl, bits)
+    qo = O.quantize(A, sl.verts, sl.vert_off, bits)
+    assert np.array_equal(ql.origin, qo.origin) and np.array_equal(ql.delta, qo.delta)
+    assert np.array_equal(ql.lowest, qo.L) and np.array_equal(ql.offsets, qo.q)
+
+
+def test_quantization_errors():
+    m = MESHES["sphere5"]()
+    sl = P.encode(m.tri, m.nverts, 64, 126)
+    A = meshgen.vertex_attributes(m)
+    with pytest.raises(P.GtsrError) as e:
+        P.quantize_attributes(A, sl, 17)
+    assert e.value.code == P.EINVAL
+    with pytest.raises(P.GtsrError) as e:
+        P.quantize_attributes(A[:10], sl, 16)       # vertex ids past the attribute rows
+    assert e.value.code == P.EINVAL
+
+
+def test_library_min_strips_equals_brute_force():
+    """Branch and bound (library) == exhaustive search (oracle) on random
+    triangle subsets of a Delaunay mesh and of a sphere."""
+    rng = np.random.default_rng(31)
+    for m in (meshgen.delaunay(300, meshgen.rng_for(4, 31)), meshgen.sphere(2, meshgen.rng_for(2, 31))):
+        for _ in range(150):
+            k = int(rng.integers(1, 15))
+            tri = m.tri[rng.choice(m.ntri, size=min(k, m.ntri), replace=False)]
+            got, proven = P.min_strips(tri)
+            assert proven and got == O.min_strips(tri)
+
+
+@pytest.mark.parametrize("caps", [(32, 64), (64, 126), (128, 256)])
+@pytest.mark.parametrize("name", ["grid64", "sphere5", "delaunay", "patch"])
+def test_exact_strips_encode_round_trips_with_fewer_restarts(name, caps):
+    m = MESHES[name]()
+    g = P.encode(m.tri, m.nverts, *caps)
+    e = P.encode(m.tri, m.nverts, *caps, exact_strips=True)
+    assert P.validate(e) == P.OK
+    assert e.stats["restarts"] <= g.stats["restarts"]
+    assert e.stats["exact_tried"] >= e.stats["exact_proven"]
+    assert e.strip_triangles == m.ntri + 4 * e.stats["restarts"]
+    s = O.Stream(e.desc_bytes, e.bits, e.reuse, e.verts, e.vert_off, e.stats)
+    np.testing.assert_array_equal(O.round_trip_triangles(s, O.decode(s)), O.canonical(m.tri))
