@@ -114,6 +114,8 @@ typedef struct gtsr_encoded_view {
   const uint32_t* kept_off;     /* meshlet_count + 1 entries: input triangles before meshlet m
                                    (strip triangles minus restart degenerates); the offsets of a
                                    compacted output (gtsr_decode_compact) */
+  const uint32_t* tri_ids;      /* input_triangles entries: the input triangles of meshlet m at
+                                   [kept_off[m], kept_off[m+1]), in strip (= compacted output) order */
   uint64_t exact_tried;         /* GTSR_ENCODE_EXACT_STRIPS: meshlets searched */
   uint64_t exact_proven;        /* ... of which the search finished (optimal strips) */
 } gtsr_encoded_view;
@@ -252,6 +254,28 @@ int gtsr_decode_gts(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes
  * skipped.  Errors: EINVAL, EHIP. */
 int gtsr_decode_compact(const gtsr_stream* dev, uint32_t format, const uint32_t* dev_kept_off, uint8_t* dev_out,
                         uint64_t out_bytes, const gtsr_launch_cfg* cfg, void* hip_stream);
+
+/* Per-meshlet normal cones for culling (Sec. 3: the amplification shader
+ * drops meshlets whose triangles all face away).  Host side: for meshlet m
+ * the input triangles tri_ids[kept_off[m] .. kept_off[m+1]) of indices
+ * (gtsr_encoded_view), vertex positions float32[vertex_count][3].  Writes
+ * cones float32[meshlet_count][4] = {axis x, y, z, cutoff}: axis = the
+ * normalised sum of the unit triangle normals (p1-p0) x (p2-p0) (zero-area
+ * triangles ignored), cutoff = sin(largest angle between axis and a normal)
+ * + 1e-5, or 2 when that angle is 90 degrees or more (never culled).
+ * Errors: EINVAL. */
+int gtsr_meshlet_cones(const uint32_t* indices, uint64_t triangle_count, const float* positions,
+                       uint32_t vertex_count, const uint32_t* tri_ids, const uint32_t* kept_off,
+                       uint32_t meshlet_count, float* cones);
+
+/* decode_meshlets with cone culling in front (GTS-Reuse format): a meshlet
+ * whose cone satisfies fmaf(az, vz, fmaf(ay, vy, ax * vx)) > cutoff (every
+ * triangle faces away from the unit view direction v) is not decoded and its
+ * output bytes are left untouched; every other meshlet decodes as in
+ * decode_meshlets.  dev_cones: device float32[meshlet_count][4], 16-byte
+ * aligned (gtsr_meshlet_cones).  Errors: EINVAL, EHIP. */
+int gtsr_decode_culled(const gtsr_stream* dev, const float* dev_cones, float view_x, float view_y, float view_z,
+                       uint8_t* dev_out, uint64_t out_bytes, const gtsr_launch_cfg* cfg, void* hip_stream);
 
 /* One plain decode launch per mesh, back to back on hip_stream: streams[i]
  * (host array of structs holding device pointers) into dev_outs[i] (host

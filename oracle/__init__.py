@@ -75,6 +75,10 @@ def lib():
     L.oracle_compact.restype = C.c_int
     L.oracle_min_strips.argtypes = [vp, C.c_uint32, u32p]
     L.oracle_min_strips.restype = C.c_int
+    L.oracle_cones.argtypes = [vp, C.c_uint32, vp, vp, vp, vp, C.c_uint32, vp]
+    L.oracle_cones.restype = C.c_int
+    L.oracle_cull.argtypes = [vp, C.c_uint32, C.c_float, C.c_float, C.c_float, vp]
+    L.oracle_cull.restype = C.c_int
     L.oracle_quantize.argtypes = [vp, C.c_uint32, C.c_uint32, vp, vp, C.c_uint32, C.c_uint32, vp, vp, vp, vp]
     L.oracle_quantize.restype = C.c_int
     L.oracle_dequantize.argtypes = [vp, vp, vp, C.c_uint32, C.c_uint32, vp, vp, vp]
@@ -236,6 +240,28 @@ def compact(decoded: np.ndarray, desc=None):
     if rc != OK:
         raise OracleError(rc)
     return out[:kept.value], offs
+
+
+def cones(s: Stream, decoded: np.ndarray, positions: np.ndarray) -> np.ndarray:
+    """Per-meshlet normal cones ``float32[M, 4]`` from decoded triples."""
+    L = lib()
+    pos = np.ascontiguousarray(positions, np.float32)
+    dec = np.ascontiguousarray(decoded, np.uint8)
+    out = np.zeros((s.meshlets, 4), np.float32)
+    rc = L.oracle_cones(_ptr(s.desc), s.meshlets, _ptr(dec), _ptr(s.verts), _ptr(s.vert_off), _ptr(pos),
+                        pos.shape[0], _ptr(out))
+    if rc != OK:
+        raise OracleError(rc)
+    return out
+
+
+def cull(cone_arr: np.ndarray, view) -> np.ndarray:
+    """``uint8[M]``: 1 where the meshlet is culled for view direction ``view``."""
+    L = lib()
+    c = np.ascontiguousarray(cone_arr, np.float32)
+    out = np.zeros(c.shape[0], np.uint8)
+    L.oracle_cull(_ptr(c), c.shape[0], float(view[0]), float(view[1]), float(view[2]), _ptr(out))
+    return out
 
 
 def min_strips(tri: np.ndarray) -> int:

@@ -61,6 +61,11 @@
  *                        that can be chained with no triangle in three pairs
  *                        (no fork) and no cycle; found by trying every subset
  *                        of pairs (brute force, tiny inputs only).
+ *   oracle_cones         Sec. 3 (cone culling in the amplification shader):
+ *   oracle_cull          per meshlet, the cone around the normalised sum of
+ *                        its triangles' unit normals that holds all of them;
+ *                        a meshlet is culled for view direction d when the
+ *                        whole cone faces away from d.
  *   oracle_compact       Drops the degenerate triangles of the restarts
  *                        (Sec. 4.2: four per restart; they are the only
  *                        triangles with a repeated index) from decoded
@@ -432,6 +437,78 @@ int oracle_dequantize(const int32_t* L, const uint16_t* q, const uint64_t* vert_
         int64_t g = (int64_t)L[(uint64_t)m * n + i] + q[k * n + i];
         out[k * n + i] = (float)fma((double)g, (double)delta[i], (double)origin[i]);
       }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------ cone culling */
+
+/*
+ * Cones from decoded meshlets: the triangles of meshlet m are its decoded
+ * triples (restart degenerates, which repeat a vertex, dropped) mapped through
+ * its vertex list to positions float32[nverts][3].  Unit normal of (p0,p1,p2):
+ * (p1-p0) x (p2-p0) normalised (zero-area triangles ignored); axis = the
+ * normalised sum of the unit normals; cos_min = the smallest dot(axis, n).
+ * Output per meshlet {axis x, y, z, cutoff} in float32 with cutoff =
+ * sqrt(1 - cos_min^2) + 1e-5 (sin of the half-angle plus a rounding margin),
+ * or 2 when cos_min <= 0 or the normals cancel (the cone is a half-space or
+ * more: never culled).
+ */
+int oracle_cones(const uint8_t* desc, uint32_t meshlet_count, const uint8_t* decoded,
+                 const uint32_t* verts, const uint64_t* vert_off, const float* pos, uint32_t nverts,
+                 float* cones) {
+  for (uint32_t m = 0; m < meshlet_count; ++m) {
+    const uint8_t* d = desc + 16ull * m;
+    uint32_t out_off = rd_u32(d + 8), T = rd_u16(d + 12);
+    double sum[3] = {0, 0, 0};
+    double* un = (double*)malloc(sizeof(double) * 3 * (T ? T : 1));
+    if (!un) return OR_ENOMEM;
+    uint32_t nu = 0;
+    for (uint32_t t = 0; t < T; ++t) {
+      const uint8_t* x = decoded + 3ull * (out_off + t);
+      if (x[0] == x[1] || x[1] == x[2] || x[0] == x[2]) continue;
+      double p[3][3];
+      for (int c = 0; c < 3; ++c) {
+        uint64_t k = vert_off[m] + x[c];
+        if (k >= vert_off[m + 1]) { free(un); return OR_ECORRUPT; }
+        uint32_t v = verts[k];
+        if (v >= nverts) { free(un); return OR_EINVAL; }
+        for (int j = 0; j < 3; ++j) p[c][j] = pos[3ull * v + j];
+      }
+      double a[3] = {p[1][0] - p[0][0], p[1][1] - p[0][1], p[1][2] - p[0][2]};
+      double b[3] = {p[2][0] - p[0][0], p[2][1] - p[0][1], p[2][2] - p[0][2]};
+      double n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+      double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      if (len == 0.0) continue;
+      for (int j = 0; j < 3; ++j) { un[3 * nu + j] = n[j] / len; sum[j] += n[j] / len; }
+      ++nu;
+    }
+    double sl = sqrt(sum[0] * sum[0] + sum[1] * sum[1] + sum[2] * sum[2]);
+    float* o = cones + 4ull * m;
+    if (nu == 0 || sl == 0.0) {
+      o[0] = o[1] = o[2] = 0.0f; o[3] = 2.0f;
+    } else {
+      double ax[3] = {sum[0] / sl, sum[1] / sl, sum[2] / sl};
+      double cmin = 1.0;
+      for (uint32_t i = 0; i < nu; ++i) {
+        double c = ax[0] * un[3 * i] + ax[1] * un[3 * i + 1] + ax[2] * un[3 * i + 2];
+        if (c < cmin) cmin = c;
+      }
+      o[0] = (float)ax[0]; o[1] = (float)ax[1]; o[2] = (float)ax[2];
+      o[3] = cmin <= 0.0 ? 2.0f : (float)(sqrt(1.0 - cmin * cmin) + 1e-5);
+    }
+    free(un);
+  }
+  return OR_OK;
+}
+
+/* Culling decision for view direction v: culled[m] = 1 when
+ * fmaf(az, vz, fmaf(ay, vy, ax * vx)) > cutoff, computed in float32. */
+int oracle_cull(const float* cones, uint32_t meshlet_count, float vx, float vy, float vz, uint8_t* culled) {
+  for (uint32_t m = 0; m < meshlet_count; ++m) {
+    const float* c = cones + 4ull * m;
+    float dot = fmaf(c[2], vz, fmaf(c[1], vy, c[0] * vx));
+    culled[m] = dot > c[3];
+  }
   return OR_OK;
 }
 

@@ -28,7 +28,8 @@ EXPORTED = (
     "gtsr_server_create", "gtsr_server_submit", "gtsr_server_poll", "gtsr_server_release",
     "gtsr_server_get_stats", "gtsr_server_replay", "gtsr_server_destroy",
     "gtsr_gts_from_reuse", "gtsr_decode_gts", "gtsr_decode_gts_batched", "gtsr_decode_compact",
-    "gtsr_quantize_attributes", "gtsr_dequantize", "gtsr_min_strips",
+    "gtsr_quantize_attributes", "gtsr_dequantize", "gtsr_min_strips", "gtsr_meshlet_cones",
+    "gtsr_decode_culled",
 )
 
 
@@ -59,7 +60,7 @@ class EncodedView(C.Structure):
                 ("reuse", C.c_void_p), ("reuse_bytes", C.c_uint64),
                 ("vertices", C.c_void_p), ("vert_off", C.c_void_p),
                 ("payload_bits", C.c_uint64), ("stored_bytes", C.c_uint64), ("kept_off", C.c_void_p),
-                ("exact_tried", C.c_uint64), ("exact_proven", C.c_uint64)]
+                ("tri_ids", C.c_void_p), ("exact_tried", C.c_uint64), ("exact_proven", C.c_uint64)]
 
 
 class StreamDesc(C.Structure):
@@ -158,6 +159,9 @@ def lib():
         "gtsr_quantize_attributes": (C.c_int, [vp, u32, u32, vp, vp, u32, u32, vp, vp, vp, vp]),
         "gtsr_dequantize": (C.c_int, [C.POINTER(AttrStream), vp, u64, C.POINTER(LaunchCfg), vp]),
         "gtsr_min_strips": (C.c_int, [vp, u32, u64, C.POINTER(u32), C.POINTER(u32)]),
+        "gtsr_meshlet_cones": (C.c_int, [vp, u64, vp, u32, vp, vp, u32, vp]),
+        "gtsr_decode_culled": (C.c_int, [C.POINTER(StreamDesc), vp, C.c_float, C.c_float, C.c_float, vp, u64,
+                                         C.POINTER(LaunchCfg), vp]),
     }
     for name, (rt, args) in sig.items():
         f = getattr(L, name)
@@ -196,6 +200,7 @@ class Encoded:
     vert_off: np.ndarray      # uint64[M+1]
     stats: dict = field(default_factory=dict)
     kept_off: np.ndarray = None   # uint32[M+1]: input triangles before each meshlet
+    tri_ids: np.ndarray = None    # uint32[T]: meshlet m's input triangles at kept_off[m]..kept_off[m+1]
     format: int = FORMAT_REUSE    # FORMAT_GTS: bits = 8-byte L/R words, reuse = index bytes
 
     @property
@@ -250,9 +255,10 @@ def encode(tri: np.ndarray, nverts: int, max_vertices: int = 64, max_triangles: 
         if exact_strips:
             stats["exact_tried"], stats["exact_proven"] = int(v.exact_tried), int(v.exact_proven)
         kept_off = take(v.kept_off, M + 1, np.uint32)
+        tri_ids = take(v.tri_ids, int(v.input_triangles) if M else 0, np.uint32)
     finally:
         L.gtsr_encoded_free(h)
-    return Encoded(meshlets, bits, reuse, verts, vert_off, stats, kept_off)
+    return Encoded(meshlets, bits, reuse, verts, vert_off, stats, kept_off, tri_ids)
 
 
 def min_strips(tri: np.ndarray, node_limit: int = 1_000_000):
@@ -262,6 +268,31 @@ def min_strips(tri: np.ndarray, node_limit: int = 1_000_000):
     _check(lib().gtsr_min_strips(tri.ctypes.data if tri.size else None, tri.shape[0], node_limit, C.byref(s),
                                  C.byref(p)))
     return int(s.value), bool(p.value)
+
+
+def meshlet_cones(tri: np.ndarray, positions: np.ndarray, enc: Encoded) -> np.ndarray:
+    """``gtsr_meshlet_cones``: float32[M, 4] {axis, cutoff} per meshlet of ``enc``
+    (the encoding of ``tri``), from vertex positions float32[V, 3]."""
+    tri = np.ascontiguousarray(tri, np.uint32).reshape(-1, 3)
+    pos = np.ascontiguousarray(positions, np.float32).reshape(-1, 3)
+    M = enc.meshlet_count
+    out = np.zeros((M, 4), np.float32)
+    ptr = lambda a: a.ctypes.data if a is not None and a.size else None
+    _check(lib().gtsr_meshlet_cones(ptr(tri), tri.shape[0], ptr(pos), pos.shape[0], ptr(enc.tri_ids),
+                                    ptr(enc.kept_off), M, ptr(out)))
+    return out
+
+
+def decode_culled(ds: DeviceStream, cones_dev, view, out=None, stream=None, cfg=None):
+    """``gtsr_decode_culled``: decode the meshlets whose cone does not face away
+    from ``view``; culled meshlets' output is left as it was."""
+    torch = _torch()
+    if out is None:
+        out = torch.zeros((ds.strip_triangles, 3), dtype=torch.uint8, device=ds.meshlets.device)
+    d = ds.desc()
+    _check(lib().gtsr_decode_culled(C.byref(d), cones_dev.data_ptr(), float(view[0]), float(view[1]),
+                                    float(view[2]), out.data_ptr(), out.numel(), _cfg(cfg), _stream_handle(stream)))
+    return out
 
 
 def gts_from_reuse(enc: Encoded) -> Encoded:
@@ -280,7 +311,7 @@ def gts_from_reuse(enc: Encoded) -> Encoded:
     stats = dict(enc.stats)
     stats["stored_bytes"] = 16 * M + words.size + index.size
     stats["payload_bits"] = enc.strip_triangles + 8 * index.size
-    return Encoded(gdesc, words, index, enc.verts, enc.vert_off, stats, enc.kept_off, FORMAT_GTS)
+    return Encoded(gdesc, words, index, enc.verts, enc.vert_off, stats, enc.kept_off, enc.tri_ids, FORMAT_GTS)
 
 
 def validate(enc: Encoded) -> int:

@@ -21,7 +21,7 @@ ARCH = os.environ.get("GTSR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")
 
-HOST_SOURCES = ["encode.cpp", "capi.cpp", "tune.cpp", "serve.cpp", "quant.cpp"]
+HOST_SOURCES = ["encode.cpp", "capi.cpp", "tune.cpp", "serve.cpp", "quant.cpp", "cones.cpp"]
 HIP_SOURCES = ["decode.hip", "attrs.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]

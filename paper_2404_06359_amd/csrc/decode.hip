@@ -113,7 +113,8 @@ __device__ __forceinline__ void store16(__amdgpu_buffer_rsrc_t r, uint32_t off, 
 // chunk, `reuse` one index byte per strip triangle after the first.  With a
 // compacted output, `kept` holds the M + 1 per-meshlet offsets among the
 // non-degenerate triangles and `out_tris` counts output triangles of that
-// output.
+// output.  With culling, `cones` holds a float4 {axis, cutoff} per meshlet and
+// `view` the view direction.
 struct Stream {
   const uint8_t* meshlets;
   const uint8_t* bits;
@@ -124,6 +125,8 @@ struct Stream {
   uint32_t reuse_bytes;
   uint32_t out_tris;
   uint32_t meshlet_count;
+  const float* cones = nullptr;
+  float view[3] = {0.0f, 0.0f, 0.0f};
 };
 
 __device__ __forceinline__ uint32_t clip32(uint64_t v) { return v > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(v); }
@@ -293,9 +296,14 @@ __device__ __forceinline__ uint2 load_kept(const Stream& s, uint32_t m, uint32_t
 // usable meshlets.  layout: the per-lane word above; with a compacted output
 // its output field is the kept offset inside the run, and o0 names the run's
 // first kept triangle.
-template <bool kPlain, bool kCompact>
+//
+// Culling: a meshlet whose normal cone faces away from the view direction
+// (dot(axis, view) > cutoff, in this float32 order) is not usable either,
+// so it is skipped and its output left untouched.
+template <bool kPlain, bool kCompact, bool kCull = false>
 __device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, const uint2& kd, uint32_t m,
-                                          uint32_t m_end, uint32_t lane, uint32_t& layout) {
+                                          uint32_t m_end, uint32_t lane, uint32_t& layout,
+                                          const uint4& cone = make_uint4(0, 0, 0, 0)) {
   const uint32_t cnt = m < m_end ? min(m_end - m, kRunMeshlets) : 0u;
   const uint32_t T = d.w & 0xFFFFu, V = d.w >> 16;
   const uint32_t nch = (T + 63) >> 6;
@@ -315,6 +323,11 @@ __device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, const
   // the run still fits the tile
   ok = ok && ex - p.c0 <= kRunChunks && ey - p.ra <= kReuseStage && ez - p.o0 <= kRunTris;
   uint32_t ot = d.z - p.o0;
+  if constexpr (kCull) {
+    const float ax = __uint_as_float(cone.x), ay = __uint_as_float(cone.y), az = __uint_as_float(cone.z);
+    const float dot = __builtin_fmaf(az, s.view[2], __builtin_fmaf(ay, s.view[1], ax * s.view[0]));
+    ok = ok && !(dot > __uint_as_float(cone.w));
+  }
   if constexpr (kCompact) {
     // kept triangles: no more than the strip triangles, so kept positions stay
     // at or before the strip positions inside the tile; the output holds them
@@ -414,18 +427,27 @@ __device__ __forceinline__ void store_nothing(uint8_t* any) {
   __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), none, int(kOutOfRange), 0, 0);
 }
 
+// Cones of meshlets [m, min(m + 32, m_end)), one float4 per lane (culling).
+__device__ __forceinline__ uint4 load_cones(const Stream& s, uint32_t m, uint32_t m_end, uint32_t lane) {
+  const uint32_t cnt = m < m_end ? min(m_end - m, kRunMeshlets) : 0u;
+  return load16(buffer(s.cones + 4ull * m, 16 * cnt), 16 * lane);
+}
+
 // Decodes meshlets [m, m_end) of stream s with the calling wavefront.
-template <bool kPlain, bool kCompact>
+template <bool kPlain, bool kCompact, bool kCull = false>
 __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32_t m_end, RunTile& tile,
                                              const LanePtrs& lp, uint32_t lane) {
   if (m >= m_end) return;
+  const uint4 zero4 = make_uint4(0, 0, 0, 0);
   uint4 d = load_descriptors(s, m, m_end, lane);
   uint2 kd = kCompact ? load_kept(s, m, m_end, lane) : make_uint2(0, 0);
+  uint4 cd = kCull ? load_cones(s, m, m_end, lane) : zero4;
   uint32_t layout;
-  Plan p = make_plan<kPlain, kCompact>(s, d, kd, m, m_end, lane, layout);
+  Plan p = make_plan<kPlain, kCompact, kCull>(s, d, kd, m, m_end, lane, layout, cd);
   uint32_t mn = m + (p.k ? p.k : 1);
   uint4 dn = load_descriptors(s, mn, m_end, lane);
   uint2 kdn = kCompact ? load_kept(s, mn, m_end, lane) : make_uint2(0, 0);
+  uint4 cdn = kCull ? load_cones(s, mn, m_end, lane) : zero4;
   uint4 bv = load_bits<kPlain>(s, p, lane);
   uint4 rv = load_reuse(s, p, lane);
   store_nothing(s.out);
@@ -434,11 +456,12 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
     reinterpret_cast<uint4*>(tile.reuse)[lane] = rv;
     // plan the next run and start its loads; they overlap this run's decode
     uint32_t layout_n;
-    const Plan pn = make_plan<kPlain, kCompact>(s, dn, kdn, mn, m_end, lane, layout_n);
+    const Plan pn = make_plan<kPlain, kCompact, kCull>(s, dn, kdn, mn, m_end, lane, layout_n, cdn);
     const uint32_t mnn = mn + (pn.k ? pn.k : 1);
     const uint32_t tri_counts = d.w & 0xFFFFu;
     const uint4 dnn = load_descriptors(s, mnn, m_end, lane);
     const uint2 kdnn = kCompact ? load_kept(s, mnn, m_end, lane) : make_uint2(0, 0);
+    const uint4 cdnn = kCull ? load_cones(s, mnn, m_end, lane) : zero4;
     const uint4 bvn = load_bits<kPlain>(s, pn, lane);
     const uint4 rvn = load_reuse(s, pn, lane);
     wave_lds_sync();
@@ -453,6 +476,7 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
     d = dn;
     dn = dnn;
     kdn = kdnn;
+    cdn = cdnn;
     bv = bvn;
     rv = rvn;
     mn = mnn;
@@ -485,11 +509,13 @@ __device__ __forceinline__ void wave_block(uint64_t n, uint32_t wave, uint32_t w
 // Plain decoder: every wavefront decodes one contiguous block of meshlets.
 // kPlain: plain GTS stream; kCompact: degenerate triangles dropped, kept
 // offsets in `kept`, out_tris counting output triangles.
-template <bool kPlain, bool kCompact>
+// kCull: meshlets whose normal cone faces away from (vx, vy, vz) are skipped.
+template <bool kPlain, bool kCompact, bool kCull = false>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
     const gtsr_meshlet* __restrict__ meshlets, const uint8_t* __restrict__ bits,
     const uint8_t* __restrict__ reuse, uint8_t* __restrict__ out, const uint32_t* __restrict__ kept,
-    uint32_t meshlet_count, uint64_t chunks, uint64_t reuse_bytes, uint64_t out_tris) {
+    uint32_t meshlet_count, uint64_t chunks, uint64_t reuse_bytes, uint64_t out_tris,
+    const float* __restrict__ cones = nullptr, float vx = 0.0f, float vy = 0.0f, float vz = 0.0f) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = uniform(threadIdx.x / kWave);
   LanePtrs lp;
@@ -498,8 +524,8 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
   wave_block(meshlet_count, wave, blockDim.x / kWave, b0, b1);
   if (b0 >= b1) return;
   const Stream s{reinterpret_cast<const uint8_t*>(meshlets), bits, reuse, out, kept,
-                 clip32(chunks), clip32(reuse_bytes), clip32(out_tris), meshlet_count};
-  decode_range<kPlain, kCompact>(s, uint32_t(b0), uint32_t(b1), tile, lp, lane);
+                 clip32(chunks), clip32(reuse_bytes), clip32(out_tris), meshlet_count, cones, {vx, vy, vz}};
+  decode_range<kPlain, kCompact, kCull>(s, uint32_t(b0), uint32_t(b1), tile, lp, lane);
 }
 
 // Persistent batched decoder: every wavefront takes one contiguous block of
@@ -723,6 +749,28 @@ extern "C" int gtsr_decode_compact(const gtsr_stream* dev, uint32_t format, cons
   if (!cus) return fail(GTSR_EHIP, std::string(who) + ": cannot query the device");
   launch_plain(dev, dev_out, out_bytes, d, cus, static_cast<hipStream_t>(hip_stream), format == GTSR_FORMAT_GTS,
                dev_kept_off);
+  return check_launch(who);
+}
+
+extern "C" int gtsr_decode_culled(const gtsr_stream* dev, const float* dev_cones, float view_x, float view_y,
+                                  float view_z, uint8_t* dev_out, uint64_t out_bytes, const gtsr_launch_cfg* cfg,
+                                  void* hip_stream) {
+  const char* who = "gtsr_decode_culled";
+  if (int rc = check_plain_args(dev, dev_out, out_bytes)) return rc;
+  if (dev->meshlet_count && !dev_cones) return fail(GTSR_EINVAL, std::string(who) + ": null cones");
+  if (reinterpret_cast<uintptr_t>(dev_cones) & 15) return fail(GTSR_EINVAL, std::string(who) + ": cones must be 16-byte aligned");
+  Defaults d;
+  if (int rc = resolve_cfg(cfg, d, who)) return rc;
+  const uint32_t cus = cu_count();
+  if (!cus) return fail(GTSR_EHIP, std::string(who) + ": cannot query the device");
+  if (dev->meshlet_count == 0) return ok();
+  const uint64_t waves = (uint64_t(dev->meshlet_count) + d.mpw - 1) / d.mpw;
+  uint64_t groups = (waves + d.waves - 1) / d.waves;
+  groups = std::min<uint64_t>(groups, uint64_t(cus) * d.gpc);
+  hipLaunchKernelGGL((k_decode_plain<false, false, true>), dim3(round_up8(groups)), dim3(kWave * d.waves),
+                     d.waves * kTileBytes, static_cast<hipStream_t>(hip_stream), dev->meshlets, dev->bits,
+                     dev->reuse, dev_out, nullptr, dev->meshlet_count, dev->bits_bytes / 16, dev->reuse_bytes,
+                     out_bytes / 3, dev_cones, view_x, view_y, view_z);
   return check_launch(who);
 }
 

@@ -32,6 +32,7 @@ struct gtsr_encoded {
   std::vector<uint32_t> verts;
   std::vector<uint64_t> vert_off;
   std::vector<uint32_t> kept_off;   // input triangles before each meshlet
+  std::vector<uint32_t> tri_ids;    // input triangle ids, meshlet by meshlet, in strip order
   uint64_t input_triangles = 0, strip_triangles = 0, restarts = 0, reuse_count = 0;
   uint64_t split_meshlets = 0, payload_bits = 0, stored_bytes = 0;
   uint64_t exact_tried = 0, exact_proven = 0;
@@ -394,6 +395,7 @@ struct Piece {   // encoder output of a contiguous meshlet range
   std::vector<uint32_t> verts;
   std::vector<uint32_t> vcount;
   std::vector<uint32_t> kept;       // input triangles per meshlet
+  std::vector<uint32_t> tri_ids;    // their ids, in strip order
   uint64_t strip_tris = 0, restarts = 0, splits = 0, payload = 0, stored = 0;
   uint64_t exact_tried = 0, exact_proven = 0;
 };
@@ -434,6 +436,7 @@ void emit_part(const uint32_t* idx, const Adjacency& A, const Stripper& st, size
     const Strip& S = st.strips[k];
     const uint32_t* tri = st.path_tri + S.first;
     const uint8_t* ex = st.path_exit + S.first;
+    P.tri_ids.insert(P.tri_ids.end(), tri, tri + S.len);
     uint32_t a, b, c;
     if (S.len == 1) {
       a = corner(idx, tri[0], 0); b = corner(idx, tri[0], 1); c = corner(idx, tri[0], 2);
@@ -712,6 +715,7 @@ extern "C" int encode_meshlets(const uint32_t* indices, uint64_t triangle_count,
       if (!P.bits.empty()) std::memcpy(E->bits.data() + chunk0 * 16, P.bits.data(), P.bits.size() * 8);
       E->reuse.insert(E->reuse.end(), P.reuse.begin(), P.reuse.end());
       E->verts.insert(E->verts.end(), P.verts.begin(), P.verts.end());
+      E->tri_ids.insert(E->tri_ids.end(), P.tri_ids.begin(), P.tri_ids.end());
       for (uint32_t v : P.vcount) { vo += v; E->vert_off.push_back(vo); }
       for (uint32_t k : P.kept) { ko += k; E->kept_off.push_back(static_cast<uint32_t>(ko)); }
       chunk0 += P.bits.size() / 2;
@@ -753,6 +757,7 @@ extern "C" int gtsr_encoded_view_get(const gtsr_encoded* e, gtsr_encoded_view* v
   v->payload_bits = e->payload_bits;
   v->stored_bytes = e->stored_bytes;
   v->kept_off = e->kept_off.data();
+  v->tri_ids = e->tri_ids.data();
   v->exact_tried = e->exact_tried;
   v->exact_proven = e->exact_proven;
   return ok();
