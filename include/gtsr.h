@@ -137,7 +137,8 @@ typedef struct gtsr_stream {
 typedef struct gtsr_launch_cfg {
   uint32_t waves_per_group;     /* 1..16: workgroup of 64*waves threads */
   uint32_t meshlets_per_wave;   /* decode_meshlets: meshlets per wavefront at least, 1..1024 */
-  uint32_t groups_per_cu;       /* groups per CU the grid is capped at, 1..32 */
+  uint32_t groups_per_cu;       /* groups per CU the grid is capped at, 1..1024 (above the
+                                   resident count, the dispatcher refills freed slots) */
   uint32_t reserved;            /* must be 0 */
 } gtsr_launch_cfg;
 
@@ -291,9 +292,10 @@ int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_ou
  * (gtsr_plan_batch); both 16-byte aligned, as must be every entry's
  * meshlets, bits and reuse pointer (entries that are not are skipped); each
  * reuse allocation must extend to a multiple of 16 bytes (as for
- * decode_meshlets).  The grid is sized to stay resident (groups_per_cu groups on
- * every CU, fewer when the list has fewer items than that grid has
- * wavefronts); each wavefront decodes one contiguous block of the work list,
+ * decode_meshlets).  The grid holds groups_per_cu groups per CU (default: 256
+ * one-wavefront groups, eight times what stays resident, so the dispatcher
+ * refills freed slots until the work runs out; fewer groups when the list has
+ * fewer items than that grid has wavefronts); each wavefront decodes one contiguous block of the work list,
  * so the list should be balanced by strip triangles (gtsr_plan_batch) and
  * have many more items than the grid has wavefronts.  No atomics, no
  * scratch memory.  Same skipping rule as decode_meshlets; items naming a
@@ -330,8 +332,9 @@ typedef struct gtsr_tune_point {
  * For every target in targets[n_targets] (strip triangles per work item,
  * i.e. meshlets per wavefront step; NULL or 0 = 384, 768, 1536, 3072) the
  * work list is planned as gtsr_plan_batch does, and for every shape in
- * cfgs[n_cfgs] (NULL or 0 = six waves-per-group x groups-per-CU pairs of 32
- * resident wavefronts per CU) one warm-up and reps timed launches
+ * cfgs[n_cfgs] (NULL or 0 = seven waves-per-group x groups-per-CU pairs: 32
+ * resident wavefronts per CU, and grids 4 and 8 times that) one warm-up and
+ * reps timed launches
  * (0 = 5, at most 1000) of decode_meshlets_batched run on hip_stream, each
  * timed with HIP events.  *best receives the point with the lowest median;
  * points (may be NULL) receives up to capacity points in measurement order

@@ -50,6 +50,10 @@ namespace {
 constexpr uint32_t kWave = 64;
 constexpr uint32_t kMaxWavesPerGroup = 16;
 constexpr uint32_t kXcds = 8;                // workgroups go round-robin over 8 XCDs
+// Grids may hold more groups than stay resident: the dispatcher refills freed
+// slots, which keeps every SIMD full until the work runs out (a SIMD issues
+// its oldest waves first, so equal static shares finish far apart).
+constexpr uint32_t kMaxGroupsPerCu = 1024;
 constexpr uint32_t kRunTris = 1024;          // strip triangles per run (LDS tile)
 constexpr uint32_t kRunMeshlets = 32;        // meshlets per run (one descriptor per lane)
 constexpr uint32_t kRunChunks = kRunTris / 64 + kRunMeshlets;   // flag chunks per run (one per lane)
@@ -590,7 +594,8 @@ int resolve_cfg(const gtsr_launch_cfg* cfg, Defaults& d, const char* who) {
     d.mpw = cfg->meshlets_per_wave;
   }
   if (cfg->groups_per_cu) {
-    if (cfg->groups_per_cu > 32) return fail(GTSR_EINVAL, std::string(who) + ": groups_per_cu > 32");
+    if (cfg->groups_per_cu > kMaxGroupsPerCu)
+      return fail(GTSR_EINVAL, std::string(who) + ": groups_per_cu > 1024");
     d.gpc = cfg->groups_per_cu;
   }
   return GTSR_OK;
@@ -627,8 +632,10 @@ int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gts
   if ((reinterpret_cast<uintptr_t>(table) & 15) || (reinterpret_cast<uintptr_t>(work) & 15))
     return fail(GTSR_EINVAL, std::string(who) + ": tables must be 16-byte aligned");
   Defaults d;
-  d.waves = 2;    // measured best for the persistent grid: 2-wave groups, 16 per CU
-  d.gpc = 16;
+  // measured best on the batched 2000-mesh workload: one-wave groups, 256 per
+  // CU (8 times the resident count, so freed slots are refilled until the end)
+  d.waves = 1;
+  d.gpc = 256;
   if (int rc = resolve_cfg(cfg, d, who)) return rc;
   const uint32_t cus = cu_count();
   if (!cus) return fail(GTSR_EHIP, std::string(who) + ": cannot query the device");

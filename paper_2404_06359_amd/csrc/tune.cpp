@@ -21,8 +21,10 @@ using namespace gtsr;
 namespace {
 
 const uint32_t kDefaultTargets[] = {384, 768, 1536, 3072};
+// Resident grids (32 waves per CU) and grids 4 and 8 times larger, which the
+// dispatcher refills as groups finish.
 const gtsr_launch_cfg kDefaultCfgs[] = {
-    {1, 0, 32, 0}, {2, 0, 16, 0}, {4, 0, 8, 0}, {8, 0, 4, 0}, {2, 0, 8, 0}, {4, 0, 4, 0},
+    {1, 0, 32, 0}, {2, 0, 16, 0}, {1, 0, 128, 0}, {1, 0, 256, 0}, {2, 0, 64, 0}, {2, 0, 128, 0}, {4, 0, 32, 0},
 };
 
 struct Events {
