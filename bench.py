@@ -184,6 +184,99 @@ def run_serve(args, threads):
     }
 
 
+def time_ms(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def line(metric, value, unit, ms, args, workload, achieved, alg, dtype="u8", **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": {"workload": workload},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": alg}}
+    out.update(extra)
+    return out
+
+
+def run_feature(args):
+    """The next-row features, each timed on its own: plain GTS batched decode
+    (the batched workload re-encoded), and on the 5.2M-triangle sphere the
+    compacted decode, the cone-culled decode and attribute dequantization."""
+    import torch
+    import meshgen
+    import paper_2404_06359_amd as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    if args.workload == "gts":
+        encs = [P.gts_from_reuse(e) for e in build_batched(args.meshes, host_threads())]
+        pool = P.Pool(encs, device=dev)
+        pool.plan(args.target_tris)
+        ms = time_ms(lambda: pool.decode_batched(stream), args.steps, args.warmup, stream)
+        alg = sum(e.meshlets.nbytes + e.bits.nbytes + e.reuse.nbytes + 3 * e.strip_triangles for e in encs)
+        tris = sum(e.stats["input_triangles"] for e in encs)
+        return line("decoded triangles/s, plain GTS batched", tris / (ms / 1e3) / 1e9, "Gtps", ms, args,
+                    "batched 2000 meshes re-encoded as plain GTS (one index byte per strip triangle), one launch",
+                    alg / (ms / 1e3) / 1e9, alg, stored_bytes=sum(e.stats["stored_bytes"] for e in encs))
+    m = meshgen.workload2()
+    enc = P.encode(m.tri, m.nverts, 64, 126, threads=0)
+    ds = P.to_device(enc, dev)
+    base_read = enc.meshlets.nbytes + enc.bits.nbytes + enc.reuse.nbytes
+    full = torch.empty((enc.strip_triangles, 3), dtype=torch.uint8, device=dev)
+    full_ms = time_ms(lambda: P.decode(ds, out=full, stream=stream), args.steps, args.warmup, stream)
+    note = "5.2M-triangle icosphere, caps 64v/126t; its streams and output fit the 256 MB last-level cache"
+    if args.workload == "compact":
+        kept = torch.from_numpy(enc.kept_off.view(np.int32).copy()).to(dev)
+        out = torch.empty((int(enc.kept_off[-1]), 3), dtype=torch.uint8, device=dev)
+        ms = time_ms(lambda: P.decode_compact(ds, kept, out=out, stream=stream), args.steps, args.warmup, stream)
+        alg = base_read + 4 * (enc.meshlet_count + 1) + 3 * int(enc.kept_off[-1])
+        return line("decoded triangles/s, compacted output", m.ntri / (ms / 1e3) / 1e9, "Gtps", ms, args,
+                    note + "; restart degenerates dropped", alg / (ms / 1e3) / 1e9, alg,
+                    uncompacted_ms=full_ms, kept_triangles=int(enc.kept_off[-1]),
+                    strip_triangles=enc.strip_triangles)
+    if args.workload == "cull":
+        pos = meshgen.vertex_attributes(m)[:, :3].copy()
+        cones = P.meshlet_cones(m.tri, pos, enc)
+        cdev = P.upload_padded(cones.view(np.uint8).reshape(-1), dev)
+        view = np.array([0.3, -0.5, 0.81], np.float32)
+        view /= np.linalg.norm(view)
+        out = torch.empty((enc.strip_triangles, 3), dtype=torch.uint8, device=dev)
+        ms = time_ms(lambda: P.decode_culled(ds, cdev, view, out=out, stream=stream), args.steps, args.warmup,
+                     stream)
+        dots = cones[:, :3].astype(np.float32) @ view
+        culled = dots > cones[:, 3]
+        T = enc.meshlets["tri_count"].astype(np.int64)
+        vis = ~culled
+        alg = (16 + 16) * enc.meshlet_count + int((16 * ((T + 63) // 64) + T + 2 -
+                                                   enc.meshlets["vert_count"].astype(np.int64))[vis].sum()) \
+            + 3 * int(T[vis].sum())
+        return line("decoded triangles/s, cone-culled decode", m.ntri / (ms / 1e3) / 1e9, "Gtps", ms, args,
+                    note + f"; view direction {view.round(3).tolist()}", alg / (ms / 1e3) / 1e9, alg,
+                    unculled_ms=full_ms, culled_meshlets=int(culled.sum()), meshlets=enc.meshlet_count)
+    # dequant
+    A = meshgen.vertex_attributes(m)
+    q = P.quantize_attributes(A, enc, 16)
+    da = P.attrs_to_device(q, dev)
+    out = torch.empty((da.elements // 8, 8), dtype=torch.float32, device=dev)
+    ms = time_ms(lambda: P.dequantize(da, out=out, stream=stream), args.steps, args.warmup, stream)
+    el = da.elements
+    alg = 2 * el + 4 * el + q.lowest.nbytes + 8 * (enc.meshlet_count + 1) + 32 * 2
+    return line("dequantized attribute values/s", el / (ms / 1e3) / 1e9, "G values/s", ms, args,
+                note + "; 8 channels (position, normal, uv), 16-bit offsets", alg / (ms / 1e3) / 1e9, alg,
+                dtype="u16->f32", meshlet_local_vertices=el // 8)
+
+
 def algorithmic_bytes(encs) -> int:
     """Per launch: every descriptor (16 B), flag chunk (16 B per 64 strip
     triangles) and reuse byte read once; 3 output bytes per strip triangle
@@ -234,7 +327,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["batched", "sphere", "serve"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "sphere", "serve", "gts", "compact", "cull", "dequant"],
+                    default="batched")
     ap.add_argument("--pool-meshes", type=int, default=5000, help="serve: pool size")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: mean requests per second")
     ap.add_argument("--requests", type=int, default=20000, help="serve: measured requests")
@@ -269,6 +363,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "serve":
         print(json.dumps(run_serve(args, host_threads())))
+        return
+    if args.workload in ("gts", "compact", "cull", "dequant"):
+        print(json.dumps(run_feature(args)))
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

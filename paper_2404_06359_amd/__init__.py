@@ -425,8 +425,10 @@ def decode_compact(ds: DeviceStream, kept_off, out=None, stream=None, cfg=None):
         total = int(kept_host[-1]) if kept_host.size else 0
     else:
         kept_dev = kept_off
-        total = int(kept_off[-1].item()) if kept_off.numel() else 0
+        total = None
     if out is None:
+        if total is None:   # reads the last offset back from the device (synchronizes)
+            total = int(kept_off[-1].item()) if kept_off.numel() else 0
         out = torch.empty((total, 3), dtype=torch.uint8, device=ds.meshlets.device)
     d = ds.desc()
     _check(L.gtsr_decode_compact(C.byref(d), ds.format, kept_dev.data_ptr(), out.data_ptr(), out.numel(),
