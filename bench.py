@@ -287,10 +287,21 @@ def algorithmic_bytes(encs) -> int:
     return total
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(encs, pool, threads):
     """The oracle's sequential strip walk over every mesh of the workload on
-    `threads` host threads (one task per mesh); its output is compared with
-    the GPU's."""
+    `threads` host threads (one task per mesh), median of 3; then once on a
+    single thread.  Its output is compared with the GPU's."""
     import oracle
 
     oracle.lib()
@@ -308,6 +319,10 @@ def cpu_baseline(encs, pool, threads):
             list(ex.map(one, order))
         times.append(time.perf_counter() - t0)
     sec = float(np.median(times))
+    t0 = time.perf_counter()
+    for i in order:
+        one(i)
+    sec1 = time.perf_counter() - t0
     gpu = pool.out.cpu().numpy()
     same = True
     for i, o in enumerate(outs):
@@ -319,7 +334,8 @@ def cpu_baseline(encs, pool, threads):
     return {"value": tris / sec / 1e9, "unit": "Gtps", "cores": threads, "kind": "oracle",
             "sample": f"whole workload ({len(encs)} meshes, {tris} input triangles), sequential strip walk, "
                       f"one task per mesh, median of 3",
-            "seconds": sec, "matches_gpu_bit_exact": same}
+            "seconds": sec, "matches_gpu_bit_exact": same, "cpu_model": cpu_model(),
+            "single_thread": {"value": tris / sec1 / 1e9, "unit": "Gtps", "seconds": sec1}}
 
 
 def main():
@@ -408,14 +424,19 @@ def main():
         step()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     ev0.record(stream)
-    for _ in range(args.steps):
+    for k in range(args.steps):
         step()
+        marks[k].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
-    log(f"[bench] {kernel}: {ms:.4f} ms per step")
+    per_step = np.array([ev0.elapsed_time(marks[0])] +
+                        [marks[k - 1].elapsed_time(marks[k]) for k in range(1, args.steps)])
+    step_pct = {f"p{q}": round(float(np.percentile(per_step, q)), 4) for q in (10, 50, 90)}
+    log(f"[bench] {kernel}: {ms:.4f} ms per step, per-step {step_pct}")
 
     per_mesh = None
     if args.workload == "batched" and not args.no_per_mesh:
@@ -429,12 +450,16 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         pm_ms = ev0.elapsed_time(ev1) / pm_steps
-        per_mesh = {"value": in_tris / (pm_ms / 1e3) / 1e9, "unit": "Gtps", "ms_per_step": pm_ms,
-                    "launches_per_step": len(encs)}
-        log(f"[bench] per-mesh plain launches: {pm_ms:.4f} ms per step")
+        per_mesh_out = pool.out.clone()
         # leave the batched result in pool.out for the baseline comparison
         step()
         torch.cuda.synchronize()
+        n_out = int(pool.out_offsets[-1])
+        same = bool(torch.equal(per_mesh_out[:n_out], pool.out[:n_out]))
+        del per_mesh_out
+        per_mesh = {"value": in_tris / (pm_ms / 1e3) / 1e9, "unit": "Gtps", "ms_per_step": pm_ms,
+                    "launches_per_step": len(encs), "output_equals_batched": same}
+        log(f"[bench] per-mesh plain launches: {pm_ms:.4f} ms per step, output equals batched: {same}")
 
     if args.calib_copy_mib:
         nbytes = args.calib_copy_mib << 20
@@ -480,6 +505,7 @@ def main():
                    "autotuned": tuned,
                    "prep_seconds": round(prep_s, 2)},
         "roofline": roof,
+        "step_ms": step_pct,
         "per_mesh": per_mesh,
         "strip_triangles_per_s": strip_tris / (ms / 1e3),
         "cpu_baseline": cpu,
