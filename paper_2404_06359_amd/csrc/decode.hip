@@ -269,15 +269,18 @@ struct Plan {
   uint32_t nch;           // flag chunks
   uint32_t ra, nrb;       // reuse staging start (16-byte aligned) and 16-byte blocks
   uint32_t tris;          // output triangles (strip triangles, or kept ones when compacting)
+  uint32_t shift;         // output start modulo 16 bytes: the tile byte of the first triangle
+  uint32_t same_nch;      // the chunk count shared by all k meshlets, else 0
 };
 
 // Per-lane layout of meshlet `lane` in the run's tile, one word:
-// bits 0..5 first flag chunk, 6..16 reuse offset, 17..28 output triangle
-// offset (triangles, < 4096), 29..30 chunk count - 1.
-__device__ __forceinline__ uint32_t pack_layout(uint32_t co, uint32_t ro, uint32_t ot, uint32_t nch) {
-  return co | (ro << 6) | (ot << 17) | ((nch - 1) << 29);
+// bits 0..5 first flag chunk, 6..16 reuse offset, 17..28 output byte offset
+// in the tile (shift + 3 * output triangle offset, < 4096), 29..30 chunk
+// count - 1.
+__device__ __forceinline__ uint32_t pack_layout(uint32_t co, uint32_t ro, uint32_t ob, uint32_t nch) {
+  return co | (ro << 6) | (ob << 17) | ((nch - 1) << 29);
 }
-static_assert(kRunChunks <= 64 && kReuseStage + 64 <= 2048 && kRunTris < 4096, "layout fields fit");
+static_assert(kRunChunks <= 64 && kReuseStage + 64 <= 2048 && 15 + 3 * (kRunTris - 1) < 4096, "layout fields fit");
 
 // Descriptors of meshlets [m, min(m + 32, m_end)), one per lane (zero past).
 __device__ __forceinline__ uint4 load_descriptors(const Stream& s, uint32_t m, uint32_t m_end, uint32_t lane) {
@@ -344,7 +347,10 @@ __device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, const
   }
   const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
   p.k = uint32_t(__builtin_ctzll(~okm));   // leading run of usable meshlets (okm has no bit past lane 31)
-  layout = pack_layout(d.x - p.c0, d.y - p.ra, ot, nch);
+  p.shift = uint32_t(reinterpret_cast<uintptr_t>(s.out) + 3 * p.o0) & 15u;
+  layout = pack_layout(d.x - p.c0, d.y - p.ra, p.shift + 3 * ot, nch);
+  const uint32_t nch0 = uniform(nch);
+  p.same_nch = p.k && !__builtin_amdgcn_ballot_w64(lane < p.k && nch != nch0) ? nch0 : 0u;
   if (p.k) {
     p.nch = lane_value(ex, p.k - 1) - p.c0;
     p.nrb = (lane_value(ey, p.k - 1) - p.ra + 15) >> 4;
@@ -373,14 +379,31 @@ __device__ __forceinline__ uint4 load_reuse(const Stream& s, const Plan& p, uint
   return load16(buffer(s.reuse + p.ra, 16 * p.nrb), 16 * lane);
 }
 
+// A run whose k meshlets all have NCH chunks: meshlet i's chunks start at
+// lane NCH * i of bv, and no meshlet needs a size dispatch.
+template <uint32_t NCH, bool kPlain, bool kCompact>
+__device__ __forceinline__ void decode_run_same(RunTile& tile, const LanePtrs& lp, uint32_t k, uint32_t layout,
+                                                uint32_t tri_counts, const uint4& bv, uint32_t lane) {
+  for (uint32_t i = 0; i < k; ++i) {
+    const uint32_t w = lane_value(layout, i);
+    const uint32_t T = kCompact ? lane_value(tri_counts, i) : 0u;
+    decode_meshlet<NCH, kPlain, kCompact>(tile, lp, bv, NCH * i, (w >> 6) & 2047u, (w >> 17) & 4095u, lane, T);
+  }
+}
+
 // Decodes the run's meshlets from the tile.  tri_counts: lane i holds meshlet
-// i's T_s (read only when compacting).
+// i's T_s (read only when compacting).  Runs of one chunk count (most runs:
+// a mesh's meshlets mostly share one size class) take a loop specialised to
+// it; the others dispatch per meshlet.
 template <bool kPlain, bool kCompact>
 __device__ __forceinline__ void decode_run(RunTile& tile, const LanePtrs& lp, const Plan& p, uint32_t layout,
-                                           uint32_t tri_counts, const uint4& bv, uint32_t shift, uint32_t lane) {
+                                           uint32_t tri_counts, const uint4& bv, uint32_t lane) {
+  if (p.same_nch == 1) return decode_run_same<1, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, bv, lane);
+  if (p.same_nch == 2) return decode_run_same<2, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, bv, lane);
+  if (p.same_nch == 4) return decode_run_same<4, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, bv, lane);
   for (uint32_t i = 0; i < p.k; ++i) {
     const uint32_t w = lane_value(layout, i);
-    const uint32_t co = w & 63u, ro = (w >> 6) & 2047u, ob = shift + 3 * ((w >> 17) & 4095u);
+    const uint32_t co = w & 63u, ro = (w >> 6) & 2047u, ob = (w >> 17) & 4095u;
     const uint32_t nch = (w >> 29) + 1;
     const uint32_t T = kCompact ? lane_value(tri_counts, i) : 0u;
     if (nch > 2) {
@@ -408,7 +431,7 @@ __device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t
   for (uint32_t q = 0; q < 4; ++q) {
     const uint32_t j = full0 + lane + kWave * q;
     const uint32_t jt = j < kOutBlocks ? j : kOutBlocks - 1;
-    store16(blocks, j < full1 ? 16 * j : kOutOfRange, tile.out[jt]);
+    store16(blocks, 16 * j, tile.out[jt]);   // blocks at or past full1 lie outside `blocks`: dropped
   }
   const uint32_t head_end = min(16 * full0, end);
   const uint32_t head = head_end - shift;
@@ -469,10 +492,8 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
     const uint4 bvn = load_bits<kPlain>(s, pn, lane);
     const uint4 rvn = load_reuse(s, pn, lane);
     wave_lds_sync();
-    uint8_t* dst = s.out + 3ull * p.o0;
-    const uint32_t shift = uint32_t(reinterpret_cast<uintptr_t>(dst)) & 15u;
-    decode_run<kPlain, kCompact>(tile, lp, p, layout, tri_counts, bv, shift, lane);
-    store_run(dst, shift, p.tris, tile, lane);
+    decode_run<kPlain, kCompact>(tile, lp, p, layout, tri_counts, bv, lane);
+    store_run(s.out + 3ull * p.o0, p.shift, p.tris, tile, lane);
     wave_lds_sync();
     if (mn >= m_end) break;
     p = pn;
