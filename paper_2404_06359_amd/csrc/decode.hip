@@ -320,37 +320,40 @@ __device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, const
   p.r0 = uniform(d.y);
   p.o0 = uniform(d.z);
   p.ra = p.r0 & ~15u;
-  // counts in range, arrays not overrun (overflow-free forms)
-  bool ok = lane < cnt && T - 1u < kMaxStripTris && V >= 3 && V <= 256 && V <= T + 2;
-  ok = ok && d.x <= s.chunks && nch <= s.chunks - d.x && d.y <= s.reuse_bytes && nru <= s.reuse_bytes - d.y;
+  // Every test below is evaluated whatever the others give (bitwise &, no
+  // short circuit), so the checks stay straight-line mask arithmetic.
+  // Counts in range (V >= 3 and V <= T + 2 as one unsigned compare, T >= 1),
+  // arrays not overrun (overflow-free forms):
+  bool ok = (lane < cnt) & (T - 1u < kMaxStripTris) & (V - 3u <= T - 1u) & (V <= 256);
+  ok &= (d.x <= s.chunks) & (nch <= s.chunks - d.x) & (d.y <= s.reuse_bytes) & (nru <= s.reuse_bytes - d.y);
   // contiguous with the meshlet before it (lane 0 starts the run)
   const uint32_t ex = d.x + nch, ey = d.y + nru, ez = d.z + T;
   const uint32_t px = from_lane_below(ex), py = from_lane_below(ey), pz = from_lane_below(ez);
-  ok = ok && (lane == 0 || (d.x == px && d.y == py && d.z == pz));
+  ok &= (lane == 0) | ((d.x == px) & (d.y == py) & (d.z == pz));
   // the run still fits the tile
-  ok = ok && ex - p.c0 <= kRunChunks && ey - p.ra <= kReuseStage && ez - p.o0 <= kRunTris;
+  ok &= (ex - p.c0 <= kRunChunks) & (ey - p.ra <= kReuseStage) & (ez - p.o0 <= kRunTris);
   uint32_t ot = d.z - p.o0;
   if constexpr (kCull) {
     const float ax = __uint_as_float(cone.x), ay = __uint_as_float(cone.y), az = __uint_as_float(cone.z);
     const float dot = __builtin_fmaf(az, s.view[2], __builtin_fmaf(ay, s.view[1], ax * s.view[0]));
-    ok = ok && !(dot > __uint_as_float(cone.w));
+    ok &= !(dot > __uint_as_float(cone.w));
   }
   if constexpr (kCompact) {
     // kept triangles: no more than the strip triangles, so kept positions stay
     // at or before the strip positions inside the tile; the output holds them
     const uint32_t kf = uniform(kd.x);
-    ok = ok && kd.y >= kd.x && kd.y - kd.x <= T && kd.x - kf <= d.z - p.o0 && kd.y <= s.out_tris;
+    ok &= (kd.y >= kd.x) & (kd.y - kd.x <= T) & (kd.x - kf <= d.z - p.o0) & (kd.y <= s.out_tris);
     ot = kd.x - kf;
     p.o0 = kf;
   } else {
-    ok = ok && d.z <= s.out_tris && T <= s.out_tris - d.z;
+    ok &= (d.z <= s.out_tris) & (T <= s.out_tris - d.z);
   }
   const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
   p.k = uint32_t(__builtin_ctzll(~okm));   // leading run of usable meshlets (okm has no bit past lane 31)
   p.shift = uint32_t(reinterpret_cast<uintptr_t>(s.out) + 3 * p.o0) & 15u;
   layout = pack_layout(d.x - p.c0, d.y - p.ra, p.shift + 3 * ot, nch);
   const uint32_t nch0 = uniform(nch);
-  p.same_nch = p.k && !__builtin_amdgcn_ballot_w64(lane < p.k && nch != nch0) ? nch0 : 0u;
+  p.same_nch = p.k && !__builtin_amdgcn_ballot_w64((lane < p.k) & (nch != nch0)) ? nch0 : 0u;
   if (p.k) {
     p.nch = lane_value(ex, p.k - 1) - p.c0;
     p.nrb = (lane_value(ey, p.k - 1) - p.ra + 15) >> 4;
@@ -481,21 +484,28 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
   for (;;) {
     // the tile is free: stage this run's reuse bytes
     reinterpret_cast<uint4*>(tile.reuse)[lane] = rv;
-    // plan the next run and start its loads; they overlap this run's decode
-    uint32_t layout_n;
-    const Plan pn = make_plan<kPlain, kCompact, kCull>(s, dn, kdn, mn, m_end, lane, layout_n, cdn);
-    const uint32_t mnn = mn + (pn.k ? pn.k : 1);
+    // plan the next run, if the range has one, and start its loads; they
+    // overlap this run's decode
+    const bool last = mn >= m_end;
+    uint32_t layout_n = 0, mnn = mn;
+    Plan pn = {};
+    uint4 dnn = zero4, cdnn = zero4, bvn = zero4, rvn = zero4;
+    uint2 kdnn = make_uint2(0, 0);
+    if (!last) {
+      pn = make_plan<kPlain, kCompact, kCull>(s, dn, kdn, mn, m_end, lane, layout_n, cdn);
+      mnn = mn + (pn.k ? pn.k : 1);
+      dnn = load_descriptors(s, mnn, m_end, lane);
+      kdnn = kCompact ? load_kept(s, mnn, m_end, lane) : make_uint2(0, 0);
+      cdnn = kCull ? load_cones(s, mnn, m_end, lane) : zero4;
+      bvn = load_bits<kPlain>(s, pn, lane);
+      rvn = load_reuse(s, pn, lane);
+    }
     const uint32_t tri_counts = d.w & 0xFFFFu;
-    const uint4 dnn = load_descriptors(s, mnn, m_end, lane);
-    const uint2 kdnn = kCompact ? load_kept(s, mnn, m_end, lane) : make_uint2(0, 0);
-    const uint4 cdnn = kCull ? load_cones(s, mnn, m_end, lane) : zero4;
-    const uint4 bvn = load_bits<kPlain>(s, pn, lane);
-    const uint4 rvn = load_reuse(s, pn, lane);
     wave_lds_sync();
     decode_run<kPlain, kCompact>(tile, lp, p, layout, tri_counts, bv, lane);
     store_run(s.out + 3ull * p.o0, p.shift, p.tris, tile, lane);
     wave_lds_sync();
-    if (mn >= m_end) break;
+    if (last) break;
     p = pn;
     layout = layout_n;
     d = dn;
