@@ -226,7 +226,10 @@ int gtsr_plan_batch(const gtsr_meshlet* const* host_meshlets, const uint32_t* me
  * strip_triangles.  dev->meshlets, dev->bits and dev->reuse must be 16-byte
  * aligned, and the reuse allocation must extend to the next multiple of 16
  * bytes past reuse_bytes (it is read in whole 16-byte blocks); the output may
- * have any alignment.
+ * have any alignment.  bits_bytes and reuse_bytes must not exceed the
+ * allocations behind dev->bits and dev->reuse: flag chunks are fetched with
+ * scalar loads, which only the descriptor checks against bits_bytes keep in
+ * bounds.
  * Enqueued on hip_stream (a hipStream_t; NULL = the null stream); returns
  * before the work finishes; allocates nothing, never synchronizes.  Meshlets whose descriptor points outside the given sizes
  * are skipped (their output bytes are left untouched); gtsr_validate reports
@@ -291,8 +294,8 @@ int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_ou
  * gtsr_mesh_entry[mesh_count]; dev_work: device gtsr_work_item[work_items]
  * (gtsr_plan_batch); both 16-byte aligned, as must be every entry's
  * meshlets, bits and reuse pointer (entries that are not are skipped); each
- * reuse allocation must extend to a multiple of 16 bytes (as for
- * decode_meshlets).  The grid holds groups_per_cu groups per CU (default: 256
+ * reuse allocation must extend to a multiple of 16 bytes, and no entry's
+ * sizes may exceed its allocations (as for decode_meshlets).  The grid holds groups_per_cu groups per CU (default: 256
  * one-wavefront groups, eight times what stays resident, so the dispatcher
  * refills freed slots until the work runs out; fewer groups when the list has
  * fewer items than that grid has wavefronts); each wavefront decodes one contiguous block of the work list,

@@ -142,12 +142,23 @@ struct Flags {
   uint64_t lr, inc;
 };
 
+// Chunk idx of a run whose first flag chunk is at g, fetched by scalar loads
+// straight into SGPRs (the constant address space marks the words uniform and
+// unchanged during the kernel).  A scalar load is not bounds-checked: every
+// chunk read lies inside the range the run's plan validated against the
+// stream's size.  The run loop has already pulled the run's chunks into L2
+// with one vector load, so these hit the cache; fetching them this way
+// instead of moving them out of that load's VGPRs with v_readlane saves four
+// VALU instructions per chunk.
+typedef __attribute__((address_space(4))) const unsigned long long ConstU64;
 template <bool kPlain>
-__device__ __forceinline__ Flags chunk_flags(const uint4& bv, uint32_t idx) {
-  Flags f;
-  f.lr = (uint64_t(lane_value(bv.y, idx)) << 32) | lane_value(bv.x, idx);
-  f.inc = kPlain ? 0ull : (uint64_t(lane_value(bv.w, idx)) << 32) | lane_value(bv.z, idx);
-  return f;
+__device__ __forceinline__ Flags chunk_flags(const uint8_t* g, uint32_t idx) {
+  if constexpr (kPlain) {
+    ConstU64* q = (ConstU64*)(g + 8ull * idx);
+    return Flags{q[0], 0ull};
+  }
+  ConstU64* q = (ConstU64*)(g + 16ull * idx);
+  return Flags{q[0], q[1]};
 }
 
 // Per-lane LDS pointers, fixed for the kernel.
@@ -225,7 +236,7 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
   o[2] = uint8_t(N);
 }
 
-// Decodes one meshlet of NCH flag chunks (in lanes co.. of bv), reuse bytes
+// Decodes one meshlet of NCH flag chunks (chunks co.. of the run at gb), reuse bytes
 // at tile.reuse[ro], output at tile byte ob.  Phase 1 writes the index slots
 // of all chunks, phase 2 reads them back, so each meshlet waits for LDS twice
 // whatever its size.  Lanes past T_s compute garbage that lands past the
@@ -235,12 +246,12 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
 // Compacted output: ob addresses the meshlet's first kept triangle and T
 // (its strip triangles) bounds the lanes that may write.
 template <uint32_t NCH, bool kPlain, bool kCompact>
-__device__ __forceinline__ void decode_meshlet(RunTile& tile, const LanePtrs& lp, const uint4& bv, uint32_t co,
+__device__ __forceinline__ void decode_meshlet(RunTile& tile, const LanePtrs& lp, const uint8_t* gb, uint32_t co,
                                                uint32_t ro, uint32_t ob, uint32_t lane, uint32_t T) {
-  Flags f0 = chunk_flags<kPlain>(bv, co), f1{0, 0}, f2{0, 0}, f3{0, 0};
-  if constexpr (NCH > 1) f1 = chunk_flags<kPlain>(bv, co + 1);
-  if constexpr (NCH > 2) f2 = chunk_flags<kPlain>(bv, co + 2);
-  if constexpr (NCH > 3) f3 = chunk_flags<kPlain>(bv, co + 3);
+  Flags f0 = chunk_flags<kPlain>(gb, co), f1{0, 0}, f2{0, 0}, f3{0, 0};
+  if constexpr (NCH > 1) f1 = chunk_flags<kPlain>(gb, co + 1);
+  if constexpr (NCH > 2) f2 = chunk_flags<kPlain>(gb, co + 2);
+  if constexpr (NCH > 3) f3 = chunk_flags<kPlain>(gb, co + 3);
   uint32_t inc_base = 2, reuse_pos = ro;
   const uint32_t n0 = new_index<kPlain, 0>(lp, f0, inc_base, reuse_pos, lane);
   uint32_t n1 = 0, n2 = 0, n3 = 0;
@@ -364,7 +375,9 @@ __device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, const
   return p;
 }
 
-// GTS-Reuse: one 16-byte chunk per lane.  Plain GTS: one 8-byte L/R word per lane.
+// The run's flag chunks, one per lane (GTS-Reuse: 16-byte chunks; plain GTS:
+// 8-byte L/R words).  Issued one run ahead, this load brings them into L2
+// for the scalar loads of the decode.
 template <bool kPlain>
 __device__ __forceinline__ uint4 load_bits(const Stream& s, const Plan& p, uint32_t lane) {
   if constexpr (kPlain) {
@@ -383,38 +396,39 @@ __device__ __forceinline__ uint4 load_reuse(const Stream& s, const Plan& p, uint
 }
 
 // A run whose k meshlets all have NCH chunks: meshlet i's chunks start at
-// lane NCH * i of bv, and no meshlet needs a size dispatch.
+// chunk NCH * i of the run, and no meshlet needs a size dispatch.
 template <uint32_t NCH, bool kPlain, bool kCompact>
 __device__ __forceinline__ void decode_run_same(RunTile& tile, const LanePtrs& lp, uint32_t k, uint32_t layout,
-                                                uint32_t tri_counts, const uint4& bv, uint32_t lane) {
+                                                uint32_t tri_counts, const uint8_t* gb, uint32_t lane) {
   for (uint32_t i = 0; i < k; ++i) {
     const uint32_t w = lane_value(layout, i);
     const uint32_t T = kCompact ? lane_value(tri_counts, i) : 0u;
-    decode_meshlet<NCH, kPlain, kCompact>(tile, lp, bv, NCH * i, (w >> 6) & 2047u, (w >> 17) & 4095u, lane, T);
+    decode_meshlet<NCH, kPlain, kCompact>(tile, lp, gb, NCH * i, (w >> 6) & 2047u, (w >> 17) & 4095u, lane, T);
   }
 }
 
-// Decodes the run's meshlets from the tile.  tri_counts: lane i holds meshlet
-// i's T_s (read only when compacting).  Runs of one chunk count (most runs:
+// Decodes the run's meshlets from the tile.  gb: the run's first flag chunk
+// in global memory; tri_counts: lane i holds meshlet i's T_s (read only when
+// compacting).  Runs of one chunk count (most runs:
 // a mesh's meshlets mostly share one size class) take a loop specialised to
 // it; the others dispatch per meshlet.
 template <bool kPlain, bool kCompact>
 __device__ __forceinline__ void decode_run(RunTile& tile, const LanePtrs& lp, const Plan& p, uint32_t layout,
-                                           uint32_t tri_counts, const uint4& bv, uint32_t lane) {
-  if (p.same_nch == 1) return decode_run_same<1, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, bv, lane);
-  if (p.same_nch == 2) return decode_run_same<2, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, bv, lane);
-  if (p.same_nch == 4) return decode_run_same<4, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, bv, lane);
+                                           uint32_t tri_counts, const uint8_t* gb, uint32_t lane) {
+  if (p.same_nch == 1) return decode_run_same<1, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, gb, lane);
+  if (p.same_nch == 2) return decode_run_same<2, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, gb, lane);
+  if (p.same_nch == 4) return decode_run_same<4, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, gb, lane);
   for (uint32_t i = 0; i < p.k; ++i) {
     const uint32_t w = lane_value(layout, i);
     const uint32_t co = w & 63u, ro = (w >> 6) & 2047u, ob = (w >> 17) & 4095u;
     const uint32_t nch = (w >> 29) + 1;
     const uint32_t T = kCompact ? lane_value(tri_counts, i) : 0u;
     if (nch > 2) {
-      if (nch > 3) decode_meshlet<4, kPlain, kCompact>(tile, lp, bv, co, ro, ob, lane, T);
-      else decode_meshlet<3, kPlain, kCompact>(tile, lp, bv, co, ro, ob, lane, T);
+      if (nch > 3) decode_meshlet<4, kPlain, kCompact>(tile, lp, gb, co, ro, ob, lane, T);
+      else decode_meshlet<3, kPlain, kCompact>(tile, lp, gb, co, ro, ob, lane, T);
     } else {
-      if (nch > 1) decode_meshlet<2, kPlain, kCompact>(tile, lp, bv, co, ro, ob, lane, T);
-      else decode_meshlet<1, kPlain, kCompact>(tile, lp, bv, co, ro, ob, lane, T);
+      if (nch > 1) decode_meshlet<2, kPlain, kCompact>(tile, lp, gb, co, ro, ob, lane, T);
+      else decode_meshlet<1, kPlain, kCompact>(tile, lp, gb, co, ro, ob, lane, T);
     }
   }
 }
@@ -502,7 +516,13 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
     }
     const uint32_t tri_counts = d.w & 0xFFFFu;
     wave_lds_sync();
-    decode_run<kPlain, kCompact>(tile, lp, p, layout, tri_counts, bv, lane);
+    // the run's flag chunks have arrived in L2 (their values are not used:
+    // the decode reads them again by scalar loads)
+    if constexpr (kPlain)
+      asm volatile("" ::"v"(bv.x), "v"(bv.y));
+    else
+      asm volatile("" ::"v"(bv.x), "v"(bv.y), "v"(bv.z), "v"(bv.w));
+    decode_run<kPlain, kCompact>(tile, lp, p, layout, tri_counts, s.bits + (kPlain ? 8ull : 16ull) * p.c0, lane);
     store_run(s.out + 3ull * p.o0, p.shift, p.tris, tile, lane);
     wave_lds_sync();
     if (last) break;
