@@ -19,12 +19,13 @@
 //   triangle      f[t] = L: (X_t, I[t+1], I[t+2]);  R: (I[t+1], X_t, I[t+2]).
 //
 // Data movement.  A wavefront decodes a contiguous block of meshlets of one
-// mesh, run by run (a run: at most 32 meshlets and kRunTris strip
+// mesh, run by run (a run: at most 32 meshlets and Shape::kTris strip
 // triangles, contiguous in all three stream arrays and in the output).  Per
-// run it loads the descriptors with one vector load, the flag chunks into
-// VGPRs (one chunk per lane) and the reuse bytes into LDS, decodes every
-// meshlet from LDS into an LDS output tile, and writes the run's output span
-// with 16-byte stores.  The runs are software-pipelined: while run j is
+// run it loads the descriptors with one vector load, the flag chunks with one
+// vector load that brings them into L2 (the decode reads each chunk into
+// SGPRs by scalar loads) and the reuse bytes into LDS, decodes every meshlet
+// from LDS into an LDS output tile, and writes the run's output span with
+// 16-byte stores.  The runs are software-pipelined: while run j is
 // decoded, the flag chunks and reuse bytes of run j+1 and the descriptors of
 // run j+2 are already in flight.  All global loads and stores are raw buffer
 // operations whose inactive lanes carry an out-of-range offset (reads return
@@ -34,8 +35,9 @@
 // Memory safety on corrupted input: a meshlet whose descriptor points outside
 // the given sizes, does not continue its predecessor contiguously, or does
 // not fit the run's tile ends the run and is skipped; buffer ranges bound
-// every global access; every LDS index is bounded by the tile sizes whatever
-// the flag bits say.
+// every global access but the scalar flag loads, which those checks keep
+// inside the stream's flag array; every LDS index is bounded by the tile
+// sizes whatever the flag bits say.
 
 #include <hip/hip_runtime.h>
 
@@ -54,22 +56,44 @@ constexpr uint32_t kXcds = 8;                // workgroups go round-robin over 8
 // slots, which keeps every SIMD full until the work runs out (a SIMD issues
 // its oldest waves first, so equal static shares finish far apart).
 constexpr uint32_t kMaxGroupsPerCu = 1024;
-constexpr uint32_t kRunTris = 1024;          // strip triangles per run (LDS tile)
 constexpr uint32_t kRunMeshlets = 32;        // meshlets per run (one descriptor per lane)
-constexpr uint32_t kRunChunks = kRunTris / 64 + kRunMeshlets;   // flag chunks per run (one per lane)
-constexpr uint32_t kReuseStage = 16 * kWave;                    // reuse bytes staged per run
-constexpr uint32_t kOutBlocks = (3 * kRunTris + 3 * 64 + 16 + 15) / 16;
-static_assert(kRunChunks <= kWave, "one flag chunk per lane");
-static_assert(kRunTris <= kReuseStage, "reuse bytes of a run fit one 16-byte block per lane (the plan also caps them)");
-static_assert(kOutBlocks <= 4 * kWave, "four 16-byte stores per lane cover the output tile");
+// LDS per wavefront: 160 KB per CU over 32 resident wavefronts (8 per SIMD).
+constexpr uint32_t kTileBudget = 160 * 1024 / 32;
+
+// Run shape per stream format.  The tile holds the run's output (3 bytes per
+// strip triangle) and its staged reuse bytes.  GTS-Reuse needs about half a
+// reuse byte per strip triangle, so its runs are longer (fewer runs, less
+// per-run work) with a smaller stage; plain GTS stages one index byte per
+// strip triangle.  A run also ends when its reuse bytes outgrow the stage.
+template <bool kPlain>
+struct Shape {
+  static constexpr uint32_t kTris = kPlain ? 1024 : 1280;        // strip triangles per run
+  static constexpr uint32_t kStage = kPlain ? 1024 : 640;        // reuse / index bytes staged per run
+  static constexpr uint32_t kChunks = kTris / 64 + kRunMeshlets; // flag chunks per run (one per lane)
+  static constexpr uint32_t kOutBlocks = (3 * kTris + 3 * 64 + 16 + 15) / 16;
+};
 
 // One wavefront's LDS tile.
+template <bool kPlain>
 struct RunTile {
-  uint4 out[kOutBlocks];                     // + a partial chunk past the run, + 16-byte shift
-  uint8_t reuse[kReuseStage + 64];           // + reads by lanes whose flags say "new"
-  uint8_t idx[272];                          // I[0 .. T_s+1] of the current meshlet
+  uint4 out[Shape<kPlain>::kOutBlocks];          // + a partial chunk past the run, + 16-byte shift
+  uint8_t reuse[Shape<kPlain>::kStage + 64];     // + reads by lanes whose flags say "new"
+  uint8_t idx[272];                              // I[0 .. T_s+1] of the current meshlet
 };
-constexpr uint32_t kTileBytes = sizeof(RunTile);
+template <bool kPlain>
+constexpr uint32_t kTileBytes = sizeof(RunTile<kPlain>);
+
+template <bool kPlain>
+constexpr bool shape_fits() {
+  using S = Shape<kPlain>;
+  return S::kChunks <= kWave                          // one flag chunk per lane
+         && S::kStage % 16 == 0 && S::kStage <= 16 * kWave   // the stage: one 16-byte block per lane at most
+         && S::kOutBlocks <= 4 * kWave                // four 16-byte stores per lane cover the output tile
+         && 3 * (kWave - 1) + 3 * S::kTris + 18 < 16 * S::kOutBlocks   // dropped compacted lanes stay in the tile
+         && S::kStage + 64 <= 2048 && 15 + 3 * (S::kTris - 1) < 4096   // layout word fields
+         && kTileBytes<kPlain> <= kTileBudget;
+}
+static_assert(shape_fits<false>() && shape_fits<true>(), "run shapes fit the tile, the layout word and the LDS budget");
 
 // The lane builtins return int; these keep every value unsigned (a signed
 // value widened into a 64-bit flag word would smear its sign bit upward).
@@ -206,7 +230,7 @@ __device__ __forceinline__ uint32_t new_index(const LanePtrs& lp, const Flags& f
 // vertices (every triangle but the four degenerates of each restart) and
 // that lie inside the meshlet write, packed in order from kept_pos; the
 // others write to the tile's spare bytes past the longest shifted run.
-template <uint32_t C, bool kCompact>
+template <uint32_t C, bool kCompact, bool kPlain>
 __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t* idx0, uint8_t* out_m,
                                               const Flags& f, uint32_t N, uint32_t lane, uint32_t& last_change,
                                               uint64_t& prev_top, uint32_t T, uint32_t& kept_pos) {
@@ -226,7 +250,7 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
     const bool keep = 64 * C + lane < T && X != P && P != N && X != N;
     const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
     const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(km >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(km), 0u));
-    o = keep ? out_m + 3 * (kept_pos + below) : lp.out + 3 * kRunTris + 16;   // past any shifted run
+    o = keep ? out_m + 3 * (kept_pos + below) : lp.out + 3 * Shape<kPlain>::kTris + 16;   // past any shifted run
     kept_pos += uint32_t(__builtin_popcountll(km));
   } else {
     o = out_m + 192 * C;
@@ -246,7 +270,7 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
 // Compacted output: ob addresses the meshlet's first kept triangle and T
 // (its strip triangles) bounds the lanes that may write.
 template <uint32_t NCH, bool kPlain, bool kCompact>
-__device__ __forceinline__ void decode_meshlet(RunTile& tile, const LanePtrs& lp, const uint8_t* gb, uint32_t co,
+__device__ __forceinline__ void decode_meshlet(RunTile<kPlain>& tile, const LanePtrs& lp, const uint8_t* gb, uint32_t co,
                                                uint32_t ro, uint32_t ob, uint32_t lane, uint32_t T) {
   Flags f0 = chunk_flags<kPlain>(gb, co), f1{0, 0}, f2{0, 0}, f3{0, 0};
   if constexpr (NCH > 1) f1 = chunk_flags<kPlain>(gb, co + 1);
@@ -263,10 +287,10 @@ __device__ __forceinline__ void decode_meshlet(RunTile& tile, const LanePtrs& lp
   uint8_t* out_m = kCompact ? reinterpret_cast<uint8_t*>(tile.out) + ob : lp.out + ob;
   uint32_t last_change = 0, kept_pos = 0;
   uint64_t prev_top = 0;
-  emit_triangle<0, kCompact>(lp, tile.idx, out_m, f0, n0, lane, last_change, prev_top, T, kept_pos);
-  if constexpr (NCH > 1) emit_triangle<1, kCompact>(lp, tile.idx, out_m, f1, n1, lane, last_change, prev_top, T, kept_pos);
-  if constexpr (NCH > 2) emit_triangle<2, kCompact>(lp, tile.idx, out_m, f2, n2, lane, last_change, prev_top, T, kept_pos);
-  if constexpr (NCH > 3) emit_triangle<3, kCompact>(lp, tile.idx, out_m, f3, n3, lane, last_change, prev_top, T, kept_pos);
+  emit_triangle<0, kCompact, kPlain>(lp, tile.idx, out_m, f0, n0, lane, last_change, prev_top, T, kept_pos);
+  if constexpr (NCH > 1) emit_triangle<1, kCompact, kPlain>(lp, tile.idx, out_m, f1, n1, lane, last_change, prev_top, T, kept_pos);
+  if constexpr (NCH > 2) emit_triangle<2, kCompact, kPlain>(lp, tile.idx, out_m, f2, n2, lane, last_change, prev_top, T, kept_pos);
+  if constexpr (NCH > 3) emit_triangle<3, kCompact, kPlain>(lp, tile.idx, out_m, f3, n3, lane, last_change, prev_top, T, kept_pos);
   wave_lds_sync();
 }
 
@@ -291,7 +315,6 @@ struct Plan {
 __device__ __forceinline__ uint32_t pack_layout(uint32_t co, uint32_t ro, uint32_t ob, uint32_t nch) {
   return co | (ro << 6) | (ob << 17) | ((nch - 1) << 29);
 }
-static_assert(kRunChunks <= 64 && kReuseStage + 64 <= 2048 && 15 + 3 * (kRunTris - 1) < 4096, "layout fields fit");
 
 // Descriptors of meshlets [m, min(m + 32, m_end)), one per lane (zero past).
 __device__ __forceinline__ uint4 load_descriptors(const Stream& s, uint32_t m, uint32_t m_end, uint32_t lane) {
@@ -342,7 +365,7 @@ __device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, const
   const uint32_t px = from_lane_below(ex), py = from_lane_below(ey), pz = from_lane_below(ez);
   ok &= (lane == 0) | ((d.x == px) & (d.y == py) & (d.z == pz));
   // the run still fits the tile
-  ok &= (ex - p.c0 <= kRunChunks) & (ey - p.ra <= kReuseStage) & (ez - p.o0 <= kRunTris);
+  ok &= (ex - p.c0 <= Shape<kPlain>::kChunks) & (ey - p.ra <= Shape<kPlain>::kStage) & (ez - p.o0 <= Shape<kPlain>::kTris);
   uint32_t ot = d.z - p.o0;
   if constexpr (kCull) {
     const float ax = __uint_as_float(cone.x), ay = __uint_as_float(cone.y), az = __uint_as_float(cone.z);
@@ -398,7 +421,7 @@ __device__ __forceinline__ uint4 load_reuse(const Stream& s, const Plan& p, uint
 // A run whose k meshlets all have NCH chunks: meshlet i's chunks start at
 // chunk NCH * i of the run, and no meshlet needs a size dispatch.
 template <uint32_t NCH, bool kPlain, bool kCompact>
-__device__ __forceinline__ void decode_run_same(RunTile& tile, const LanePtrs& lp, uint32_t k, uint32_t layout,
+__device__ __forceinline__ void decode_run_same(RunTile<kPlain>& tile, const LanePtrs& lp, uint32_t k, uint32_t layout,
                                                 uint32_t tri_counts, const uint8_t* gb, uint32_t lane) {
   for (uint32_t i = 0; i < k; ++i) {
     const uint32_t w = lane_value(layout, i);
@@ -413,7 +436,7 @@ __device__ __forceinline__ void decode_run_same(RunTile& tile, const LanePtrs& l
 // a mesh's meshlets mostly share one size class) take a loop specialised to
 // it; the others dispatch per meshlet.
 template <bool kPlain, bool kCompact>
-__device__ __forceinline__ void decode_run(RunTile& tile, const LanePtrs& lp, const Plan& p, uint32_t layout,
+__device__ __forceinline__ void decode_run(RunTile<kPlain>& tile, const LanePtrs& lp, const Plan& p, uint32_t layout,
                                            uint32_t tri_counts, const uint8_t* gb, uint32_t lane) {
   if (p.same_nch == 1) return decode_run_same<1, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, gb, lane);
   if (p.same_nch == 2) return decode_run_same<2, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, gb, lane);
@@ -437,7 +460,8 @@ __device__ __forceinline__ void decode_run(RunTile& tile, const LanePtrs& lp, co
 // tris (shift = dst mod 16): the 16-byte blocks inside the span with four
 // stores per lane, then the ragged bytes at the two ends (at most 15 each)
 // with one byte store per lane.
-__device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t tris, const RunTile& tile,
+template <bool kPlain>
+__device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t tris, const RunTile<kPlain>& tile,
                                           uint32_t lane) {
   uint8_t* base = dst - shift;                      // 16-byte aligned, tile byte 0
   const uint32_t end = shift + 3 * tris;
@@ -447,6 +471,7 @@ __device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t
 #pragma unroll
   for (uint32_t q = 0; q < 4; ++q) {
     const uint32_t j = full0 + lane + kWave * q;
+    constexpr uint32_t kOutBlocks = Shape<kPlain>::kOutBlocks;
     const uint32_t jt = j < kOutBlocks ? j : kOutBlocks - 1;
     store16(blocks, 16 * j, tile.out[jt]);   // blocks at or past full1 lie outside `blocks`: dropped
   }
@@ -455,7 +480,7 @@ __device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t
   const uint32_t tail_start = max(16 * full1, head_end);
   const uint32_t tail = end - tail_start;
   const uint32_t pos = lane < head ? shift + lane : tail_start + (lane - head);
-  const uint32_t byte = reinterpret_cast<const uint8_t*>(tile.out)[pos < 16 * kOutBlocks ? pos : 0];
+  const uint32_t byte = reinterpret_cast<const uint8_t*>(tile.out)[pos < sizeof(tile.out) ? pos : 0];
   __builtin_amdgcn_raw_buffer_store_b8(uint8_t(byte), buffer(base, end), int(lane < head + tail ? pos : kOutOfRange),
                                        0, 0);
 }
@@ -479,7 +504,7 @@ __device__ __forceinline__ uint4 load_cones(const Stream& s, uint32_t m, uint32_
 
 // Decodes meshlets [m, m_end) of stream s with the calling wavefront.
 template <bool kPlain, bool kCompact, bool kCull = false>
-__device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32_t m_end, RunTile& tile,
+__device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32_t m_end, RunTile<kPlain>& tile,
                                              const LanePtrs& lp, uint32_t lane) {
   if (m >= m_end) return;
   const uint4 zero4 = make_uint4(0, 0, 0, 0);
@@ -497,7 +522,7 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
   store_nothing(s.out);
   for (;;) {
     // the tile is free: stage this run's reuse bytes
-    reinterpret_cast<uint4*>(tile.reuse)[lane] = rv;
+    if (lane < Shape<kPlain>::kStage / 16) reinterpret_cast<uint4*>(tile.reuse)[lane] = rv;
     // plan the next run, if the range has one, and start its loads; they
     // overlap this run's decode
     const bool last = mn >= m_end;
@@ -523,7 +548,7 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
     else
       asm volatile("" ::"v"(bv.x), "v"(bv.y), "v"(bv.z), "v"(bv.w));
     decode_run<kPlain, kCompact>(tile, lp, p, layout, tri_counts, s.bits + (kPlain ? 8ull : 16ull) * p.c0, lane);
-    store_run(s.out + 3ull * p.o0, p.shift, p.tris, tile, lane);
+    store_run<kPlain>(s.out + 3ull * p.o0, p.shift, p.tris, tile, lane);
     wave_lds_sync();
     if (last) break;
     p = pn;
@@ -538,9 +563,10 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
   }
 }
 
-__device__ __forceinline__ RunTile& wave_tile(uint32_t wave, uint32_t lane, LanePtrs& lp) {
+template <bool kPlain>
+__device__ __forceinline__ RunTile<kPlain>& wave_tile(uint32_t wave, uint32_t lane, LanePtrs& lp) {
   extern __shared__ uint4 lds_tiles[];
-  RunTile& tile = reinterpret_cast<RunTile*>(lds_tiles)[wave];
+  RunTile<kPlain>& tile = reinterpret_cast<RunTile<kPlain>*>(lds_tiles)[wave];
   if (lane < 3) tile.idx[lane] = uint8_t(lane);
   lp.reuse = tile.reuse + lane;
   lp.idx = tile.idx + lane;
@@ -574,7 +600,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = uniform(threadIdx.x / kWave);
   LanePtrs lp;
-  RunTile& tile = wave_tile(wave, lane, lp);
+  RunTile<kPlain>& tile = wave_tile<kPlain>(wave, lane, lp);
   uint64_t b0, b1;
   wave_block(meshlet_count, wave, blockDim.x / kWave, b0, b1);
   if (b0 >= b1) return;
@@ -594,7 +620,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = uniform(threadIdx.x / kWave);
   LanePtrs lp;
-  RunTile& tile = wave_tile(wave, lane, lp);
+  RunTile<kPlain>& tile = wave_tile<kPlain>(wave, lane, lp);
   uint64_t b0, b1;
   wave_block(work_items, wave, blockDim.x / kWave, b0, b1);
   for (uint64_t base = b0; base < b1; base += kWave) {
@@ -695,10 +721,10 @@ int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gts
   const uint64_t want = (uint64_t(work_items) + d.waves - 1) / d.waves;
   const uint32_t groups = round_up8(std::min<uint64_t>(uint64_t(cus) * d.gpc, want));
   if (plain)
-    hipLaunchKernelGGL(k_decode_batched<true>, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes, stream,
+    hipLaunchKernelGGL(k_decode_batched<true>, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes<true>, stream,
                        table, mesh_count, work, work_items);
   else
-    hipLaunchKernelGGL(k_decode_batched<false>, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes, stream,
+    hipLaunchKernelGGL(k_decode_batched<false>, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes<false>, stream,
                        table, mesh_count, work, work_items);
   return check_launch(who);
 }
@@ -726,7 +752,7 @@ int launch_plain(const gtsr_stream* dev, uint8_t* dev_out, uint64_t out_bytes, c
   uint64_t groups = (waves + d.waves - 1) / d.waves;
   groups = std::min<uint64_t>(groups, uint64_t(cus) * d.gpc);
   const dim3 grid(round_up8(groups)), block(kWave * d.waves);
-  const uint32_t lds = d.waves * kTileBytes;
+  const uint32_t lds = d.waves * (plain ? kTileBytes<true> : kTileBytes<false>);
   const uint64_t chunks = dev->bits_bytes / (plain ? 8 : 16);
 #define GTSR_LAUNCH_PLAIN(P, K)                                                                                   \
   hipLaunchKernelGGL((k_decode_plain<P, K>), grid, block, lds, stream, dev->meshlets, dev->bits, dev->reuse, dev_out, \
@@ -826,7 +852,7 @@ extern "C" int gtsr_decode_culled(const gtsr_stream* dev, const float* dev_cones
   uint64_t groups = (waves + d.waves - 1) / d.waves;
   groups = std::min<uint64_t>(groups, uint64_t(cus) * d.gpc);
   hipLaunchKernelGGL((k_decode_plain<false, false, true>), dim3(round_up8(groups)), dim3(kWave * d.waves),
-                     d.waves * kTileBytes, static_cast<hipStream_t>(hip_stream), dev->meshlets, dev->bits,
+                     d.waves * kTileBytes<false>, static_cast<hipStream_t>(hip_stream), dev->meshlets, dev->bits,
                      dev->reuse, dev_out, nullptr, dev->meshlet_count, dev->bits_bytes / 16, dev->reuse_bytes,
                      out_bytes / 3, dev_cones, view_x, view_y, view_z);
   return check_launch(who);
