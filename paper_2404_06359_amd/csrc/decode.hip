@@ -130,10 +130,16 @@ __device__ __forceinline__ uint4 load16(__amdgpu_buffer_rsrc_t r, uint32_t off) 
   return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// Cache policy of the output stores: non-temporal (the nt bit of gfx950's
+// cache-policy field).  The kernel writes its output once and never reads it,
+// so the stores should not displace from L2 the flag chunks that each run
+// prefetches for the scalar loads of its decode.
+constexpr int kOutputPolicy = 2;
+
 __device__ __forceinline__ void store16(__amdgpu_buffer_rsrc_t r, uint32_t off, const uint4& w) {
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   const u32x4 v = {w.x, w.y, w.z, w.w};
-  __builtin_amdgcn_raw_buffer_store_b128(v, r, int(off), 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, int(off), 0, kOutputPolicy);
 }
 
 // One mesh's stream.  GTS-Reuse: `bits` holds 16-byte chunks {LR, INC},
@@ -482,7 +488,7 @@ __device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t
   const uint32_t pos = lane < head ? shift + lane : tail_start + (lane - head);
   const uint32_t byte = reinterpret_cast<const uint8_t*>(tile.out)[pos < sizeof(tile.out) ? pos : 0];
   __builtin_amdgcn_raw_buffer_store_b8(uint8_t(byte), buffer(base, end), int(lane < head + tail ? pos : kOutOfRange),
-                                       0, 0);
+                                       0, kOutputPolicy);
 }
 
 // The same five stores store_run issues, all out of range: they write
@@ -493,7 +499,7 @@ __device__ __forceinline__ void store_nothing(uint8_t* any) {
   const __amdgpu_buffer_rsrc_t none = buffer(any, 0);
 #pragma unroll
   for (uint32_t q = 0; q < 4; ++q) store16(none, kOutOfRange + 16 * q, make_uint4(q, 0, 0, 0));
-  __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), none, int(kOutOfRange), 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), none, int(kOutOfRange), 0, kOutputPolicy);
 }
 
 // Cones of meshlets [m, min(m + 32, m_end)), one float4 per lane (culling).
