@@ -248,7 +248,10 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
   if (C != 0 && !upto) px = idx0 + last_change;
   if (C == 0 || ch) last_change = 64 * C + 63 - uint32_t(__builtin_clzll(ch));   // else: no flip in this chunk
   prev_top = f.lr >> 63;
-  const uint32_t P = at_t[1];
+  // I[t+1]: the new slot of the lane below.  In a meshlet's first chunk lane 0
+  // takes I[1] = 1, so a DPP shift replaces the LDS read; later chunks read
+  // the slot their lane 0 needs from the chunk before.
+  const uint32_t P = C == 0 ? uint32_t(__builtin_amdgcn_update_dpp(1, int(N), 0x138, 0xF, 0xF, false)) : at_t[1];
   const uint32_t X = *px;
   const bool right = __builtin_amdgcn_inverse_ballot_w64(f.lr);
   uint8_t* o;
