@@ -401,9 +401,10 @@ typedef struct gtsr_server_stats {
  * the out field is ignored, outputs go to the arena); host_meshlets[i]: mesh
  * i's host descriptors (read during this call only, to plan its work items).
  * The pool's device arrays must outlive the server.  Creates max_inflight HIP
- * streams (default priority), pinned and device staging of max_batch table
- * rows and max_items work items per slot, and the scheduler thread, all on
- * the current device.  Errors: EINVAL, ENOMEM, EHIP. */
+ * streams (default priority), pinned coherent host memory for max_batch table
+ * rows and max_items work items per slot (the decode kernel reads a batch's
+ * table and work list from there, with no copy), and the scheduler thread,
+ * all on the current device.  Errors: EINVAL, ENOMEM, EHIP. */
 int gtsr_server_create(const gtsr_mesh_entry* host_table, const gtsr_meshlet* const* host_meshlets,
                        uint32_t mesh_count, const gtsr_server_params* params, gtsr_server** server);
 

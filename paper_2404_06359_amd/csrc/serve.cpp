@@ -5,8 +5,10 @@
 // requests in arrival order while their decoded output (3 bytes per strip
 // triangle) fits into the caller's output arena -- the HBM budget for
 // in-flight outputs -- and a launch slot is free.  Each slot owns a HIP stream
-// (default priority), pinned staging and device copies of one batch's mesh
-// table and work list.  The requests admitted together go out as one
+// (default priority) and one batch's mesh table and work list in pinned,
+// coherent host memory that the kernel reads directly (no copy: a
+// host-to-device copy call blocked the scheduler for milliseconds now and
+// then).  The requests admitted together go out as one
 // decode_meshlets_batched launch on that slot's stream, so up to
 // `max_inflight` batches run on the device at once, and requests that arrive
 // while others decode are admitted as soon as a slot and arena space free up.
@@ -96,9 +98,9 @@ struct Request {
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  gtsr_mesh_entry* h_table = nullptr;
+  gtsr_mesh_entry* h_table = nullptr;   // pinned, coherent host memory
   gtsr_work_item* h_work = nullptr;
-  gtsr_mesh_entry* d_table = nullptr;
+  gtsr_mesh_entry* d_table = nullptr;   // the same memory, as the device addresses it
   gtsr_work_item* d_work = nullptr;
   std::vector<Request> reqs;
   bool busy = false;
@@ -170,8 +172,6 @@ void free_slot(Slot& s) {
   if (s.stream) (void)hipStreamDestroy(s.stream);
   if (s.h_table) (void)hipHostFree(s.h_table);
   if (s.h_work) (void)hipHostFree(s.h_work);
-  if (s.d_table) (void)hipFree(s.d_table);
-  if (s.d_work) (void)hipFree(s.d_work);
   s = Slot{};
 }
 
@@ -246,14 +246,11 @@ bool gtsr_server::admit_and_launch() {
     stats.max_batch_seen = std::max<uint64_t>(stats.max_batch_seen, slot->reqs.size());
     stats.max_arena_used = std::max<uint64_t>(stats.max_arena_used, arena.used());
   }
+  // The table and work list were written above, before the launch: the kernel
+  // reads them from host memory.
   const uint32_t rows = uint32_t(slot->reqs.size());
-  hipError_t e = hipMemcpyAsync(slot->d_table, slot->h_table, rows * sizeof(gtsr_mesh_entry),
-                                hipMemcpyHostToDevice, slot->stream);
-  if (e == hipSuccess && items)
-    e = hipMemcpyAsync(slot->d_work, slot->h_work, items * sizeof(gtsr_work_item), hipMemcpyHostToDevice,
-                       slot->stream);
-  int rc = e == hipSuccess ? decode_meshlets_batched(slot->d_table, rows, slot->d_work, items, &p.cfg, slot->stream)
-                           : GTSR_EHIP;
+  hipError_t e = hipSuccess;
+  int rc = decode_meshlets_batched(slot->d_table, rows, slot->d_work, items, &p.cfg, slot->stream);
   if (rc == GTSR_OK) {
     e = hipEventRecord(slot->done, slot->stream);
     if (e != hipSuccess) rc = GTSR_EHIP;
@@ -360,10 +357,13 @@ extern "C" int gtsr_server_create(const gtsr_mesh_entry* host_table, const gtsr_
   for (Slot& sl : s->slots) {
     hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_table), p.max_batch * sizeof(gtsr_mesh_entry));
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_work), p.max_items * sizeof(gtsr_work_item));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d_table), p.max_batch * sizeof(gtsr_mesh_entry));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d_work), p.max_items * sizeof(gtsr_work_item));
+    const unsigned host_flags = hipHostMallocMapped | hipHostMallocCoherent;
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_table), p.max_batch * sizeof(gtsr_mesh_entry), host_flags);
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_work), p.max_items * sizeof(gtsr_work_item), host_flags);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.d_table), sl.h_table, 0);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.d_work), sl.h_work, 0);
     if (e != hipSuccess) {
       rc = hip_fail(who, "slot resources", e);
       break;
