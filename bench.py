@@ -410,7 +410,7 @@ def main():
             t0 = time.perf_counter()
             cfg, best, points = pool.autotune(stream=stream)
             tuned = {"target_tris": best["target_tris"], "waves_per_group": best["waves_per_group"],
-                     "groups_per_cu": best["groups_per_cu"], "points": len(points),
+                     "groups_per_cu": best["groups_per_cu"], "run_tris": best["run_tris"], "points": len(points),
                      "seconds": round(time.perf_counter() - t0, 2)}
             log(f"[bench] autotune: {len(points)} shapes, best {best}")
         graph = pool.batched_graph(cfg)

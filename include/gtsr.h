@@ -139,7 +139,9 @@ typedef struct gtsr_launch_cfg {
   uint32_t meshlets_per_wave;   /* decode_meshlets: meshlets per wavefront at least, 1..1024 */
   uint32_t groups_per_cu;       /* groups per CU the grid is capped at, 1..1024 (above the
                                    resident count, the dispatcher refills freed slots) */
-  uint32_t reserved;            /* must be 0 */
+  uint32_t run_tris;            /* batched decoders: the LDS tile, as strip triangles per run:
+                                   0 = default, 1280 or 1024 (GTS-Reuse), 1024 (plain GTS);
+                                   every other decoder: must be 0 */
 } gtsr_launch_cfg;
 
 /* One row of the batched decoder's mesh table (device memory, 64 bytes):
@@ -326,17 +328,18 @@ int gtsr_batched_graph_create(const gtsr_mesh_entry* dev_mesh_table, uint32_t me
 typedef struct gtsr_tune_point {
   uint32_t target_tris;       /* gtsr_plan_batch target the work list was built with */
   uint32_t work_items;        /* items in that work list */
-  gtsr_launch_cfg cfg;        /* waves_per_group, groups_per_cu (meshlets_per_wave unused) */
+  gtsr_launch_cfg cfg;        /* waves_per_group, groups_per_cu, run_tris (meshlets_per_wave unused) */
   float median_ms, min_ms;    /* over the timed launches */
 } gtsr_tune_point;
 
-/* Pick the batched decoder's launch shape by measurement (the paper decodes
- * one meshlet per workgroup and has no such knob).
+/* Pick the batched decoder's launch shape and LDS tile by measurement (the
+ * paper decodes one meshlet per workgroup and has no such knob).
  * For every target in targets[n_targets] (strip triangles per work item,
  * i.e. meshlets per wavefront step; NULL or 0 = 384, 768, 1536, 3072) the
  * work list is planned as gtsr_plan_batch does, and for every shape in
  * cfgs[n_cfgs] (NULL or 0 = seven waves-per-group x groups-per-CU pairs: 32
- * resident wavefronts per CU, and grids 4 and 8 times that) one warm-up and
+ * resident wavefronts per CU, and grids 4 and 8 times that, each with
+ * run_tris 1280 and 1024: fourteen shapes) one warm-up and
  * reps timed launches
  * (0 = 5, at most 1000) of decode_meshlets_batched run on hip_stream, each
  * timed with HIP events.  *best receives the point with the lowest median;

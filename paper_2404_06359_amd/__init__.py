@@ -72,7 +72,7 @@ class StreamDesc(C.Structure):
 
 class LaunchCfg(C.Structure):
     _fields_ = [("waves_per_group", C.c_uint32), ("meshlets_per_wave", C.c_uint32),
-                ("groups_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
+                ("groups_per_cu", C.c_uint32), ("run_tris", C.c_uint32)]
 
 
 class TunePoint(C.Structure):
@@ -82,7 +82,7 @@ class TunePoint(C.Structure):
     def as_dict(self) -> dict:
         return {"target_tris": self.target_tris, "work_items": self.work_items,
                 "waves_per_group": self.cfg.waves_per_group, "groups_per_cu": self.cfg.groups_per_cu,
-                "median_ms": self.median_ms, "min_ms": self.min_ms}
+                "run_tris": self.cfg.run_tris, "median_ms": self.median_ms, "min_ms": self.min_ms}
 
 
 class AttrStream(C.Structure):
@@ -183,7 +183,7 @@ def _cfg(cfg) -> C.POINTER(LaunchCfg):
     if isinstance(cfg, LaunchCfg):
         return C.byref(cfg)
     c = LaunchCfg(int(cfg.get("waves_per_group", 0)), int(cfg.get("meshlets_per_wave", 0)),
-                  int(cfg.get("groups_per_cu", 0)), 0)
+                  int(cfg.get("groups_per_cu", 0)), int(cfg.get("run_tris", 0)))
     return C.byref(c)
 
 
@@ -604,8 +604,9 @@ class Pool:
         tg = np.array(targets or [], np.uint32)
         cf = (LaunchCfg * max(len(cfgs or []), 1))()
         for i, c in enumerate(cfgs or []):
-            cf[i] = LaunchCfg(int(c.get("waves_per_group", 0)), 0, int(c.get("groups_per_cu", 0)), 0)
-        cap = max(1, len(tg) or 4) * max(1, len(cfgs or []) or 7)
+            cf[i] = LaunchCfg(int(c.get("waves_per_group", 0)), 0, int(c.get("groups_per_cu", 0)),
+                              int(c.get("run_tris", 0)))
+        cap = max(1, len(tg) or 4) * max(1, len(cfgs or []) or 14)
         pts = (TunePoint * cap)()
         cnt = C.c_uint32()
         best = TunePoint()
@@ -614,7 +615,8 @@ class Pool:
                                        cf if cfgs else None, len(cfgs or []), reps, pts, cap, C.byref(cnt),
                                        C.byref(best), _stream_handle(stream)))
         self.plan(int(best.target_tris))
-        cfg = {"waves_per_group": int(best.cfg.waves_per_group), "groups_per_cu": int(best.cfg.groups_per_cu)}
+        cfg = {"waves_per_group": int(best.cfg.waves_per_group), "groups_per_cu": int(best.cfg.groups_per_cu),
+               "run_tris": int(best.cfg.run_tris)}
         return cfg, best.as_dict(), [pts[i].as_dict() for i in range(min(cnt.value, cap))]
 
     def decode_batched(self, stream=None, cfg=None):
@@ -657,7 +659,8 @@ class Server:
         self._arena_base = (base + 255) // 256 * 256
         c = LaunchCfg(0, 0, 0, 0)
         if cfg:
-            c = LaunchCfg(int(cfg.get("waves_per_group", 0)), 0, int(cfg.get("groups_per_cu", 0)), 0)
+            c = LaunchCfg(int(cfg.get("waves_per_group", 0)), 0, int(cfg.get("groups_per_cu", 0)),
+                          int(cfg.get("run_tris", 0)))
         p = ServerParams(self._arena_base, int(arena_bytes), max_inflight, max_batch, target_tris, max_items,
                          c, 0, 0)
         n = pool.mesh_count

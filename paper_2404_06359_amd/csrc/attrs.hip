@@ -61,7 +61,7 @@ extern "C" int gtsr_dequantize(const gtsr_attr_stream* dev, float* dev_out, uint
   const char* who = "gtsr_dequantize";
   if (!dev) return fail(GTSR_EINVAL, std::string(who) + ": null stream");
   if (dev->channels == 0 || dev->channels > 64) return fail(GTSR_EINVAL, std::string(who) + ": channels must be 1..64");
-  if (cfg && cfg->reserved) return fail(GTSR_EINVAL, std::string(who) + ": cfg.reserved must be 0");
+  if (cfg && cfg->run_tris) return fail(GTSR_EINVAL, std::string(who) + ": cfg.run_tris must be 0");
   if (dev->meshlet_count == 0) return ok();
   if (!dev->lowest || !dev->offsets || !dev->vert_off || !dev->origin || !dev->delta || !dev_out)
     return fail(GTSR_EINVAL, std::string(who) + ": null device pointer");

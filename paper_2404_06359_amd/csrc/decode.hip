@@ -60,40 +60,44 @@ constexpr uint32_t kRunMeshlets = 32;        // meshlets per run (one descriptor
 // LDS per wavefront: 160 KB per CU over 32 resident wavefronts (8 per SIMD).
 constexpr uint32_t kTileBudget = 160 * 1024 / 32;
 
-// Run shape per stream format.  The tile holds the run's output (3 bytes per
-// strip triangle) and its staged reuse bytes.  GTS-Reuse needs about half a
-// reuse byte per strip triangle, so its runs are longer (fewer runs, less
-// per-run work) with a smaller stage; plain GTS stages one index byte per
-// strip triangle.  A run also ends when its reuse bytes outgrow the stage.
-template <bool kPlain>
+// Run shape per stream format and tile choice.  The tile holds the run's
+// output (3 bytes per strip triangle) and its staged reuse bytes.  GTS-Reuse
+// needs about half a reuse byte per strip triangle, so its default tile
+// (kTile 0) takes longer runs (fewer runs, less per-run work) with a smaller
+// stage; kTile 1 is the 1024-triangle run with a 1024-byte stage, which plain
+// GTS always uses (one index byte per strip triangle).  A run also ends when
+// its reuse bytes outgrow the stage.
+template <bool kPlain, uint32_t kTile = 0>
 struct Shape {
-  static constexpr uint32_t kTris = kPlain ? 1024 : 1280;        // strip triangles per run
-  static constexpr uint32_t kStage = kPlain ? 1024 : 640;        // reuse / index bytes staged per run
+  static constexpr bool kShort = kPlain || kTile == 1;
+  static constexpr uint32_t kTris = kShort ? 1024 : 1280;        // strip triangles per run
+  static constexpr uint32_t kStage = kShort ? 1024 : 640;        // reuse / index bytes staged per run
   static constexpr uint32_t kChunks = kTris / 64 + kRunMeshlets; // flag chunks per run (one per lane)
   static constexpr uint32_t kOutBlocks = (3 * kTris + 3 * 64 + 16 + 15) / 16;
 };
 
 // One wavefront's LDS tile.
-template <bool kPlain>
+template <bool kPlain, uint32_t kTile = 0>
 struct RunTile {
-  uint4 out[Shape<kPlain>::kOutBlocks];          // + a partial chunk past the run, + 16-byte shift
-  uint8_t reuse[Shape<kPlain>::kStage + 64];     // + reads by lanes whose flags say "new"
-  uint8_t idx[272];                              // I[0 .. T_s+1] of the current meshlet
+  uint4 out[Shape<kPlain, kTile>::kOutBlocks];          // + a partial chunk past the run, + 16-byte shift
+  uint8_t reuse[Shape<kPlain, kTile>::kStage + 64];     // + reads by lanes whose flags say "new"
+  uint8_t idx[272];                                     // I[0 .. T_s+1] of the current meshlet
 };
-template <bool kPlain>
-constexpr uint32_t kTileBytes = sizeof(RunTile<kPlain>);
+template <bool kPlain, uint32_t kTile = 0>
+constexpr uint32_t kTileBytes = sizeof(RunTile<kPlain, kTile>);
 
-template <bool kPlain>
+template <bool kPlain, uint32_t kTile>
 constexpr bool shape_fits() {
-  using S = Shape<kPlain>;
+  using S = Shape<kPlain, kTile>;
   return S::kChunks <= kWave                          // one flag chunk per lane
          && S::kStage % 16 == 0 && S::kStage <= 16 * kWave   // the stage: one 16-byte block per lane at most
          && S::kOutBlocks <= 4 * kWave                // four 16-byte stores per lane cover the output tile
          && 3 * (kWave - 1) + 3 * S::kTris + 18 < 16 * S::kOutBlocks   // dropped compacted lanes stay in the tile
          && S::kStage + 64 <= 2048 && 15 + 3 * (S::kTris - 1) < 4096   // layout word fields
-         && kTileBytes<kPlain> <= kTileBudget;
+         && kTileBytes<kPlain, kTile> <= kTileBudget;
 }
-static_assert(shape_fits<false>() && shape_fits<true>(), "run shapes fit the tile, the layout word and the LDS budget");
+static_assert(shape_fits<false, 0>() && shape_fits<false, 1>() && shape_fits<true, 0>(),
+              "run shapes fit the tile, the layout word and the LDS budget");
 
 // The lane builtins return int; these keep every value unsigned (a signed
 // value widened into a 64-bit flag word would smear its sign bit upward).
@@ -236,7 +240,7 @@ __device__ __forceinline__ uint32_t new_index(const LanePtrs& lp, const Flags& f
 // vertices (every triangle but the four degenerates of each restart) and
 // that lie inside the meshlet write, packed in order from kept_pos; the
 // others write to the tile's spare bytes past the longest shifted run.
-template <uint32_t C, bool kCompact, bool kPlain>
+template <uint32_t C, bool kCompact, bool kPlain, uint32_t kTile>
 __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t* idx0, uint8_t* out_m,
                                               const Flags& f, uint32_t N, uint32_t lane, uint32_t& last_change,
                                               uint64_t& prev_top, uint32_t T, uint32_t& kept_pos) {
@@ -259,7 +263,7 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
     const bool keep = 64 * C + lane < T && X != P && P != N && X != N;
     const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
     const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(km >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(km), 0u));
-    o = keep ? out_m + 3 * (kept_pos + below) : lp.out + 3 * Shape<kPlain>::kTris + 16;   // past any shifted run
+    o = keep ? out_m + 3 * (kept_pos + below) : lp.out + 3 * Shape<kPlain, kTile>::kTris + 16;   // past any shifted run
     kept_pos += uint32_t(__builtin_popcountll(km));
   } else {
     o = out_m + 192 * C;
@@ -278,8 +282,8 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
 //
 // Compacted output: ob addresses the meshlet's first kept triangle and T
 // (its strip triangles) bounds the lanes that may write.
-template <uint32_t NCH, bool kPlain, bool kCompact>
-__device__ __forceinline__ void decode_meshlet(RunTile<kPlain>& tile, const LanePtrs& lp, const uint8_t* gb, uint32_t co,
+template <uint32_t NCH, bool kPlain, bool kCompact, uint32_t kTile>
+__device__ __forceinline__ void decode_meshlet(RunTile<kPlain, kTile>& tile, const LanePtrs& lp, const uint8_t* gb, uint32_t co,
                                                uint32_t ro, uint32_t ob, uint32_t lane, uint32_t T) {
   Flags f0 = chunk_flags<kPlain>(gb, co), f1{0, 0}, f2{0, 0}, f3{0, 0};
   if constexpr (NCH > 1) f1 = chunk_flags<kPlain>(gb, co + 1);
@@ -296,10 +300,10 @@ __device__ __forceinline__ void decode_meshlet(RunTile<kPlain>& tile, const Lane
   uint8_t* out_m = kCompact ? reinterpret_cast<uint8_t*>(tile.out) + ob : lp.out + ob;
   uint32_t last_change = 0, kept_pos = 0;
   uint64_t prev_top = 0;
-  emit_triangle<0, kCompact, kPlain>(lp, tile.idx, out_m, f0, n0, lane, last_change, prev_top, T, kept_pos);
-  if constexpr (NCH > 1) emit_triangle<1, kCompact, kPlain>(lp, tile.idx, out_m, f1, n1, lane, last_change, prev_top, T, kept_pos);
-  if constexpr (NCH > 2) emit_triangle<2, kCompact, kPlain>(lp, tile.idx, out_m, f2, n2, lane, last_change, prev_top, T, kept_pos);
-  if constexpr (NCH > 3) emit_triangle<3, kCompact, kPlain>(lp, tile.idx, out_m, f3, n3, lane, last_change, prev_top, T, kept_pos);
+  emit_triangle<0, kCompact, kPlain, kTile>(lp, tile.idx, out_m, f0, n0, lane, last_change, prev_top, T, kept_pos);
+  if constexpr (NCH > 1) emit_triangle<1, kCompact, kPlain, kTile>(lp, tile.idx, out_m, f1, n1, lane, last_change, prev_top, T, kept_pos);
+  if constexpr (NCH > 2) emit_triangle<2, kCompact, kPlain, kTile>(lp, tile.idx, out_m, f2, n2, lane, last_change, prev_top, T, kept_pos);
+  if constexpr (NCH > 3) emit_triangle<3, kCompact, kPlain, kTile>(lp, tile.idx, out_m, f3, n3, lane, last_change, prev_top, T, kept_pos);
   wave_lds_sync();
 }
 
@@ -350,7 +354,7 @@ __device__ __forceinline__ uint2 load_kept(const Stream& s, uint32_t m, uint32_t
 // Culling: a meshlet whose normal cone faces away from the view direction
 // (dot(axis, view) > cutoff, in this float32 order) is not usable either,
 // so it is skipped and its output left untouched.
-template <bool kPlain, bool kCompact, bool kCull = false>
+template <bool kPlain, bool kCompact, bool kCull, uint32_t kTile>
 __device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, const uint2& kd, uint32_t m,
                                           uint32_t m_end, uint32_t lane, uint32_t& layout,
                                           const uint4& cone = make_uint4(0, 0, 0, 0)) {
@@ -374,7 +378,8 @@ __device__ __forceinline__ Plan make_plan(const Stream& s, const uint4& d, const
   const uint32_t px = from_lane_below(ex), py = from_lane_below(ey), pz = from_lane_below(ez);
   ok &= (lane == 0) | ((d.x == px) & (d.y == py) & (d.z == pz));
   // the run still fits the tile
-  ok &= (ex - p.c0 <= Shape<kPlain>::kChunks) & (ey - p.ra <= Shape<kPlain>::kStage) & (ez - p.o0 <= Shape<kPlain>::kTris);
+  using S = Shape<kPlain, kTile>;
+  ok &= (ex - p.c0 <= S::kChunks) & (ey - p.ra <= S::kStage) & (ez - p.o0 <= S::kTris);
   uint32_t ot = d.z - p.o0;
   if constexpr (kCull) {
     const float ax = __uint_as_float(cone.x), ay = __uint_as_float(cone.y), az = __uint_as_float(cone.z);
@@ -429,13 +434,13 @@ __device__ __forceinline__ uint4 load_reuse(const Stream& s, const Plan& p, uint
 
 // A run whose k meshlets all have NCH chunks: meshlet i's chunks start at
 // chunk NCH * i of the run, and no meshlet needs a size dispatch.
-template <uint32_t NCH, bool kPlain, bool kCompact>
-__device__ __forceinline__ void decode_run_same(RunTile<kPlain>& tile, const LanePtrs& lp, uint32_t k, uint32_t layout,
+template <uint32_t NCH, bool kPlain, bool kCompact, uint32_t kTile>
+__device__ __forceinline__ void decode_run_same(RunTile<kPlain, kTile>& tile, const LanePtrs& lp, uint32_t k, uint32_t layout,
                                                 uint32_t tri_counts, const uint8_t* gb, uint32_t lane) {
   for (uint32_t i = 0; i < k; ++i) {
     const uint32_t w = lane_value(layout, i);
     const uint32_t T = kCompact ? lane_value(tri_counts, i) : 0u;
-    decode_meshlet<NCH, kPlain, kCompact>(tile, lp, gb, NCH * i, (w >> 6) & 2047u, (w >> 17) & 4095u, lane, T);
+    decode_meshlet<NCH, kPlain, kCompact, kTile>(tile, lp, gb, NCH * i, (w >> 6) & 2047u, (w >> 17) & 4095u, lane, T);
   }
 }
 
@@ -444,23 +449,23 @@ __device__ __forceinline__ void decode_run_same(RunTile<kPlain>& tile, const Lan
 // compacting).  Runs of one chunk count (most runs:
 // a mesh's meshlets mostly share one size class) take a loop specialised to
 // it; the others dispatch per meshlet.
-template <bool kPlain, bool kCompact>
-__device__ __forceinline__ void decode_run(RunTile<kPlain>& tile, const LanePtrs& lp, const Plan& p, uint32_t layout,
+template <bool kPlain, bool kCompact, uint32_t kTile>
+__device__ __forceinline__ void decode_run(RunTile<kPlain, kTile>& tile, const LanePtrs& lp, const Plan& p, uint32_t layout,
                                            uint32_t tri_counts, const uint8_t* gb, uint32_t lane) {
-  if (p.same_nch == 1) return decode_run_same<1, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, gb, lane);
-  if (p.same_nch == 2) return decode_run_same<2, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, gb, lane);
-  if (p.same_nch == 4) return decode_run_same<4, kPlain, kCompact>(tile, lp, p.k, layout, tri_counts, gb, lane);
+  if (p.same_nch == 1) return decode_run_same<1, kPlain, kCompact, kTile>(tile, lp, p.k, layout, tri_counts, gb, lane);
+  if (p.same_nch == 2) return decode_run_same<2, kPlain, kCompact, kTile>(tile, lp, p.k, layout, tri_counts, gb, lane);
+  if (p.same_nch == 4) return decode_run_same<4, kPlain, kCompact, kTile>(tile, lp, p.k, layout, tri_counts, gb, lane);
   for (uint32_t i = 0; i < p.k; ++i) {
     const uint32_t w = lane_value(layout, i);
     const uint32_t co = w & 63u, ro = (w >> 6) & 2047u, ob = (w >> 17) & 4095u;
     const uint32_t nch = (w >> 29) + 1;
     const uint32_t T = kCompact ? lane_value(tri_counts, i) : 0u;
     if (nch > 2) {
-      if (nch > 3) decode_meshlet<4, kPlain, kCompact>(tile, lp, gb, co, ro, ob, lane, T);
-      else decode_meshlet<3, kPlain, kCompact>(tile, lp, gb, co, ro, ob, lane, T);
+      if (nch > 3) decode_meshlet<4, kPlain, kCompact, kTile>(tile, lp, gb, co, ro, ob, lane, T);
+      else decode_meshlet<3, kPlain, kCompact, kTile>(tile, lp, gb, co, ro, ob, lane, T);
     } else {
-      if (nch > 1) decode_meshlet<2, kPlain, kCompact>(tile, lp, gb, co, ro, ob, lane, T);
-      else decode_meshlet<1, kPlain, kCompact>(tile, lp, gb, co, ro, ob, lane, T);
+      if (nch > 1) decode_meshlet<2, kPlain, kCompact, kTile>(tile, lp, gb, co, ro, ob, lane, T);
+      else decode_meshlet<1, kPlain, kCompact, kTile>(tile, lp, gb, co, ro, ob, lane, T);
     }
   }
 }
@@ -469,8 +474,8 @@ __device__ __forceinline__ void decode_run(RunTile<kPlain>& tile, const LanePtrs
 // tris (shift = dst mod 16): the 16-byte blocks inside the span with four
 // stores per lane, then the ragged bytes at the two ends (at most 15 each)
 // with one byte store per lane.
-template <bool kPlain>
-__device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t tris, const RunTile<kPlain>& tile,
+template <bool kPlain, uint32_t kTile>
+__device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t tris, const RunTile<kPlain, kTile>& tile,
                                           uint32_t lane) {
   uint8_t* base = dst - shift;                      // 16-byte aligned, tile byte 0
   const uint32_t end = shift + 3 * tris;
@@ -480,7 +485,7 @@ __device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t
 #pragma unroll
   for (uint32_t q = 0; q < 4; ++q) {
     const uint32_t j = full0 + lane + kWave * q;
-    constexpr uint32_t kOutBlocks = Shape<kPlain>::kOutBlocks;
+    constexpr uint32_t kOutBlocks = Shape<kPlain, kTile>::kOutBlocks;
     const uint32_t jt = j < kOutBlocks ? j : kOutBlocks - 1;
     store16(blocks, 16 * j, tile.out[jt]);   // blocks at or past full1 lie outside `blocks`: dropped
   }
@@ -512,8 +517,8 @@ __device__ __forceinline__ uint4 load_cones(const Stream& s, uint32_t m, uint32_
 }
 
 // Decodes meshlets [m, m_end) of stream s with the calling wavefront.
-template <bool kPlain, bool kCompact, bool kCull = false>
-__device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32_t m_end, RunTile<kPlain>& tile,
+template <bool kPlain, bool kCompact, bool kCull, uint32_t kTile>
+__device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32_t m_end, RunTile<kPlain, kTile>& tile,
                                              const LanePtrs& lp, uint32_t lane) {
   if (m >= m_end) return;
   const uint4 zero4 = make_uint4(0, 0, 0, 0);
@@ -521,7 +526,7 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
   uint2 kd = kCompact ? load_kept(s, m, m_end, lane) : make_uint2(0, 0);
   uint4 cd = kCull ? load_cones(s, m, m_end, lane) : zero4;
   uint32_t layout;
-  Plan p = make_plan<kPlain, kCompact, kCull>(s, d, kd, m, m_end, lane, layout, cd);
+  Plan p = make_plan<kPlain, kCompact, kCull, kTile>(s, d, kd, m, m_end, lane, layout, cd);
   uint32_t mn = m + (p.k ? p.k : 1);
   uint4 dn = load_descriptors(s, mn, m_end, lane);
   uint2 kdn = kCompact ? load_kept(s, mn, m_end, lane) : make_uint2(0, 0);
@@ -531,7 +536,7 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
   store_nothing(s.out);
   for (;;) {
     // the tile is free: stage this run's reuse bytes
-    if (lane < Shape<kPlain>::kStage / 16) reinterpret_cast<uint4*>(tile.reuse)[lane] = rv;
+    if (lane < Shape<kPlain, kTile>::kStage / 16) reinterpret_cast<uint4*>(tile.reuse)[lane] = rv;
     // plan the next run, if the range has one, and start its loads; they
     // overlap this run's decode
     const bool last = mn >= m_end;
@@ -540,7 +545,7 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
     uint4 dnn = zero4, cdnn = zero4, bvn = zero4, rvn = zero4;
     uint2 kdnn = make_uint2(0, 0);
     if (!last) {
-      pn = make_plan<kPlain, kCompact, kCull>(s, dn, kdn, mn, m_end, lane, layout_n, cdn);
+      pn = make_plan<kPlain, kCompact, kCull, kTile>(s, dn, kdn, mn, m_end, lane, layout_n, cdn);
       mnn = mn + (pn.k ? pn.k : 1);
       dnn = load_descriptors(s, mnn, m_end, lane);
       kdnn = kCompact ? load_kept(s, mnn, m_end, lane) : make_uint2(0, 0);
@@ -556,8 +561,8 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
       asm volatile("" ::"v"(bv.x), "v"(bv.y));
     else
       asm volatile("" ::"v"(bv.x), "v"(bv.y), "v"(bv.z), "v"(bv.w));
-    decode_run<kPlain, kCompact>(tile, lp, p, layout, tri_counts, s.bits + (kPlain ? 8ull : 16ull) * p.c0, lane);
-    store_run<kPlain>(s.out + 3ull * p.o0, p.shift, p.tris, tile, lane);
+    decode_run<kPlain, kCompact, kTile>(tile, lp, p, layout, tri_counts, s.bits + (kPlain ? 8ull : 16ull) * p.c0, lane);
+    store_run<kPlain, kTile>(s.out + 3ull * p.o0, p.shift, p.tris, tile, lane);
     wave_lds_sync();
     if (last) break;
     p = pn;
@@ -572,10 +577,10 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
   }
 }
 
-template <bool kPlain>
-__device__ __forceinline__ RunTile<kPlain>& wave_tile(uint32_t wave, uint32_t lane, LanePtrs& lp) {
+template <bool kPlain, uint32_t kTile>
+__device__ __forceinline__ RunTile<kPlain, kTile>& wave_tile(uint32_t wave, uint32_t lane, LanePtrs& lp) {
   extern __shared__ uint4 lds_tiles[];
-  RunTile<kPlain>& tile = reinterpret_cast<RunTile<kPlain>*>(lds_tiles)[wave];
+  RunTile<kPlain, kTile>& tile = reinterpret_cast<RunTile<kPlain, kTile>*>(lds_tiles)[wave];
   if (lane < 3) tile.idx[lane] = uint8_t(lane);
   lp.reuse = tile.reuse + lane;
   lp.idx = tile.idx + lane;
@@ -600,7 +605,7 @@ __device__ __forceinline__ void wave_block(uint64_t n, uint32_t wave, uint32_t w
 // kPlain: plain GTS stream; kCompact: degenerate triangles dropped, kept
 // offsets in `kept`, out_tris counting output triangles.
 // kCull: meshlets whose normal cone faces away from (vx, vy, vz) are skipped.
-template <bool kPlain, bool kCompact, bool kCull = false>
+template <bool kPlain, bool kCompact, bool kCull = false, uint32_t kTile = 0>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
     const gtsr_meshlet* __restrict__ meshlets, const uint8_t* __restrict__ bits,
     const uint8_t* __restrict__ reuse, uint8_t* __restrict__ out, const uint32_t* __restrict__ kept,
@@ -609,27 +614,27 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = uniform(threadIdx.x / kWave);
   LanePtrs lp;
-  RunTile<kPlain>& tile = wave_tile<kPlain>(wave, lane, lp);
+  RunTile<kPlain, kTile>& tile = wave_tile<kPlain, kTile>(wave, lane, lp);
   uint64_t b0, b1;
   wave_block(meshlet_count, wave, blockDim.x / kWave, b0, b1);
   if (b0 >= b1) return;
   const Stream s{reinterpret_cast<const uint8_t*>(meshlets), bits, reuse, out, kept,
                  clip32(chunks), clip32(reuse_bytes), clip32(out_tris), meshlet_count, cones, {vx, vy, vz}};
-  decode_range<kPlain, kCompact, kCull>(s, uint32_t(b0), uint32_t(b1), tile, lp, lane);
+  decode_range<kPlain, kCompact, kCull, kTile>(s, uint32_t(b0), uint32_t(b1), tile, lp, lane);
 }
 
 // Persistent batched decoder: every wavefront takes one contiguous block of
 // the work list (items are balanced by strip triangles) and decodes it as
 // meshlet ranges, merging consecutive items that continue the same mesh.
 // kPlain: every entry holds a plain GTS stream.
-template <bool kPlain>
+template <bool kPlain, uint32_t kTile>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
     const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
     const gtsr_work_item* __restrict__ work, uint32_t work_items) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = uniform(threadIdx.x / kWave);
   LanePtrs lp;
-  RunTile<kPlain>& tile = wave_tile<kPlain>(wave, lane, lp);
+  RunTile<kPlain, kTile>& tile = wave_tile<kPlain, kTile>(wave, lane, lp);
   uint64_t b0, b1;
   wave_block(work_items, wave, blockDim.x / kWave, b0, b1);
   for (uint64_t base = b0; base < b1; base += kWave) {
@@ -659,18 +664,27 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
                      clip32(e.bits_bytes / (kPlain ? 8 : 16)), clip32(e.reuse_bytes), clip32(e.strip_triangles),
                      e.meshlet_count};
       const uint32_t stop = min(end, e.meshlet_count);
-      if (first < stop) decode_range<kPlain, false>(s, first, stop, tile, lp, lane);
+      if (first < stop) decode_range<kPlain, false, false, kTile>(s, first, stop, tile, lp, lane);
     }
   }
 }
 
 struct Defaults {
   uint32_t waves = 4, mpw = 8, gpc = 8;
+  uint32_t tile = 0;   // Shape tile index; GTS-Reuse: 0 = 1280-triangle runs, 1 = 1024
 };
 
-int resolve_cfg(const gtsr_launch_cfg* cfg, Defaults& d, const char* who) {
+// run_tris (batched decoders only): 0 = the default tile, else the run
+// length of a compiled tile (1280 or 1024 for GTS-Reuse, 1024 for plain GTS).
+int resolve_cfg(const gtsr_launch_cfg* cfg, Defaults& d, const char* who, bool batched = false,
+                bool plain = false) {
   if (!cfg) return GTSR_OK;
-  if (cfg->reserved) return fail(GTSR_EINVAL, std::string(who) + ": cfg.reserved must be 0");
+  if (cfg->run_tris) {
+    if (!batched) return fail(GTSR_EINVAL, std::string(who) + ": cfg.run_tris must be 0 (batched decoders only)");
+    if (cfg->run_tris == Shape<false, 1>::kTris) d.tile = 1;
+    else if (plain || cfg->run_tris != Shape<false, 0>::kTris)
+      return fail(GTSR_EINVAL, std::string(who) + ": cfg.run_tris must be 0, 1024 or (GTS-Reuse) 1280");
+  }
   if (cfg->waves_per_group) {
     if (cfg->waves_per_group > kMaxWavesPerGroup) return fail(GTSR_EINVAL, std::string(who) + ": waves_per_group > 16");
     d.waves = cfg->waves_per_group;
@@ -722,7 +736,7 @@ int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gts
   // CU (8 times the resident count, so freed slots are refilled until the end)
   d.waves = 1;
   d.gpc = 256;
-  if (int rc = resolve_cfg(cfg, d, who)) return rc;
+  if (int rc = resolve_cfg(cfg, d, who, true, plain)) return rc;
   const uint32_t cus = cu_count();
   if (!cus) return fail(GTSR_EHIP, std::string(who) + ": cannot query the device");
   if (work_items == 0) return ok();
@@ -730,11 +744,14 @@ int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gts
   const uint64_t want = (uint64_t(work_items) + d.waves - 1) / d.waves;
   const uint32_t groups = round_up8(std::min<uint64_t>(uint64_t(cus) * d.gpc, want));
   if (plain)
-    hipLaunchKernelGGL(k_decode_batched<true>, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes<true>, stream,
-                       table, mesh_count, work, work_items);
+    hipLaunchKernelGGL((k_decode_batched<true, 0>), dim3(groups), dim3(kWave * d.waves), d.waves * (kTileBytes<true, 0>),
+                       stream, table, mesh_count, work, work_items);
+  else if (d.tile == 1)
+    hipLaunchKernelGGL((k_decode_batched<false, 1>), dim3(groups), dim3(kWave * d.waves), d.waves * (kTileBytes<false, 1>),
+                       stream, table, mesh_count, work, work_items);
   else
-    hipLaunchKernelGGL(k_decode_batched<false>, dim3(groups), dim3(kWave * d.waves), d.waves * kTileBytes<false>, stream,
-                       table, mesh_count, work, work_items);
+    hipLaunchKernelGGL((k_decode_batched<false, 0>), dim3(groups), dim3(kWave * d.waves), d.waves * (kTileBytes<false, 0>),
+                       stream, table, mesh_count, work, work_items);
   return check_launch(who);
 }
 

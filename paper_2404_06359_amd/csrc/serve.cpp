@@ -331,7 +331,8 @@ extern "C" int gtsr_server_create(const gtsr_mesh_entry* host_table, const gtsr_
   if (p.target_tris == 0) p.target_tris = 768;
   if (p.max_items == 0) p.max_items = 1u << 20;
   if (p.max_inflight > 8 || p.max_batch > 65536 || p.max_items > (1u << 26) || p.reserved || p.reserved2 ||
-      p.cfg.reserved || p.cfg.waves_per_group > 16 || p.cfg.groups_per_cu > 1024)
+      (p.cfg.run_tris != 0 && p.cfg.run_tris != 1024 && p.cfg.run_tris != 1280) || p.cfg.waves_per_group > 16 ||
+      p.cfg.groups_per_cu > 1024)
     return fail(GTSR_EINVAL, std::string(who) + ": parameter out of range");
   auto* s = new (std::nothrow) gtsr_server(p.arena_bytes);
   if (!s) return fail(GTSR_ENOMEM, std::string(who) + ": out of memory");

@@ -22,9 +22,12 @@ namespace {
 
 const uint32_t kDefaultTargets[] = {384, 768, 1536, 3072};
 // Resident grids (32 waves per CU) and grids 4 and 8 times larger, which the
-// dispatcher refills as groups finish.
+// dispatcher refills as groups finish, each with both LDS tiles (1280- and
+// 1024-triangle runs).
 const gtsr_launch_cfg kDefaultCfgs[] = {
-    {1, 0, 32, 0}, {2, 0, 16, 0}, {1, 0, 128, 0}, {1, 0, 256, 0}, {2, 0, 64, 0}, {2, 0, 128, 0}, {4, 0, 32, 0},
+    {1, 0, 32, 1280}, {2, 0, 16, 1280}, {1, 0, 128, 1280}, {1, 0, 256, 1280}, {2, 0, 64, 1280},
+    {2, 0, 128, 1280}, {4, 0, 32, 1280}, {1, 0, 32, 1024}, {2, 0, 16, 1024}, {1, 0, 128, 1024},
+    {1, 0, 256, 1024}, {2, 0, 64, 1024}, {2, 0, 128, 1024}, {4, 0, 32, 1024},
 };
 
 struct Events {

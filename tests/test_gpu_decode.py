@@ -176,7 +176,8 @@ def test_batched_persistent(target):
         refs.append(O.decode(s))
     streams = [device_stream(s.desc, s.bits, s.reuse, s.strip_triangles) for s in encs]
     host = [s.desc.view(P.MESHLET_DTYPE) for s in encs]
-    for cfg in (None, {"waves_per_group": 1, "groups_per_cu": 1}, {"waves_per_group": 16, "groups_per_cu": 2}):
+    for cfg in (None, {"waves_per_group": 1, "groups_per_cu": 1}, {"waves_per_group": 16, "groups_per_cu": 2},
+                {"run_tris": 1024}, {"waves_per_group": 2, "groups_per_cu": 3, "run_tris": 1280}):
         say(f"[gpu] batched target={target} cfg={cfg}")
         b = P.Batch(streams, target_tris=target, host_meshlets=host)
         b.out_all.fill_(0xAA)
@@ -212,16 +213,18 @@ def test_autotune_picks_a_measured_shape_and_keeps_outputs():
     libencs = [P.encode(m.tri, m.nverts, *caps) for m, caps in _batched_meshes()]
     pool = P.Pool(libencs)
     pool.out.fill_(0xAA)
-    cfgs = [{"waves_per_group": 1, "groups_per_cu": 4}, {"waves_per_group": 4, "groups_per_cu": 2}]
-    say("[gpu] autotune 2 targets x 2 shapes")
+    cfgs = [{"waves_per_group": 1, "groups_per_cu": 4, "run_tris": 1024},
+            {"waves_per_group": 4, "groups_per_cu": 2, "run_tris": 1280}, {"waves_per_group": 2, "groups_per_cu": 8}]
+    say("[gpu] autotune 2 targets x 3 shapes")
     cfg, best, points = pool.autotune(targets=[200, 3000], cfgs=cfgs, reps=3)
     torch.cuda.synchronize()
-    assert len(points) == 4
-    assert {(p["target_tris"], p["waves_per_group"], p["groups_per_cu"]) for p in points} == \
-        {(t, c["waves_per_group"], c["groups_per_cu"]) for t in (200, 3000) for c in cfgs}
+    assert len(points) == 6
+    assert {(p["target_tris"], p["waves_per_group"], p["groups_per_cu"], p["run_tris"]) for p in points} == \
+        {(t, c["waves_per_group"], c["groups_per_cu"], c.get("run_tris", 0)) for t in (200, 3000) for c in cfgs}
     assert best["median_ms"] == min(p["median_ms"] for p in points)
     assert pool.work_items == best["work_items"]
-    assert cfg == {"waves_per_group": best["waves_per_group"], "groups_per_cu": best["groups_per_cu"]}
+    assert cfg == {"waves_per_group": best["waves_per_group"], "groups_per_cu": best["groups_per_cu"],
+                   "run_tris": best["run_tris"]}
     for i, ref in enumerate(refs):
         np.testing.assert_array_equal(pool.output(i).cpu().numpy(), ref)
     pool.out.fill_(0x55)

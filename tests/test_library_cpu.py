@@ -219,6 +219,26 @@ def test_gts_from_reuse_errors():
     assert rc == P.EINVAL
 
 
+def test_launch_cfg_run_tris_validation():
+    """run_tris picks one of the compiled LDS tiles for the batched decoders
+    (1280 or 1024 strip triangles per GTS-Reuse run, 1024 for plain GTS) and
+    must be 0 everywhere else.  The checks run before any device call."""
+    L = P.lib()
+    for bad in (1, 768, 1152, 2048):
+        c = P.LaunchCfg(0, 0, 0, bad)
+        assert L.decode_meshlets_batched(None, 0, None, 0, ctypes.byref(c), None) == P.EINVAL
+        assert "run_tris" in L.gtsr_last_error().decode()
+    c = P.LaunchCfg(0, 0, 0, 1280)
+    assert L.gtsr_decode_gts_batched(None, 0, None, 0, ctypes.byref(c), None) == P.EINVAL
+    empty = P.StreamDesc(None, None, None, 0, 0, 0, 0, 0)
+    for tiles in (1024, 1280):
+        c = P.LaunchCfg(0, 0, 0, tiles)
+        assert L.gtsr_decode_meshlets_cfg(ctypes.byref(empty), None, 0, ctypes.byref(c), None) == P.EINVAL
+        assert L.gtsr_decode_gts(ctypes.byref(empty), None, 0, ctypes.byref(c), None) == P.EINVAL
+        attrs = P.AttrStream(None, None, None, None, None, 1, 1)
+        assert L.gtsr_dequantize(ctypes.byref(attrs), None, 0, ctypes.byref(c), None) == P.EINVAL
+
+
 @pytest.mark.parametrize("bits", [16, 10])
 @pytest.mark.parametrize("caps", [(32, 64), (128, 256)])
 @pytest.mark.parametrize("name", ["sphere5", "delaunay"])
