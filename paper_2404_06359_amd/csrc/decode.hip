@@ -626,7 +626,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
 // Persistent batched decoder: every wavefront takes one contiguous block of
 // the work list (items are balanced by strip triangles) and decodes it as
 // meshlet ranges, merging consecutive items that continue the same mesh.
-// kPlain: every entry holds a plain GTS stream.
+// kPlain: every entry holds a plain GTS stream; kTile: the LDS tile (Shape).
 template <bool kPlain, uint32_t kTile>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
     const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
