@@ -200,6 +200,7 @@ struct LanePtrs {
   const uint8_t* reuse;   // tile.reuse + lane
   uint8_t* idx;           // tile.idx + lane
   uint8_t* out;           // tile.out + 3 * lane
+  uint32_t lane0;         // 1 in lane 0, else 0
 };
 
 // Phase 1 for chunk C: the new slot I[t+2] -- the next vertex number, or the
@@ -215,35 +216,34 @@ __device__ __forceinline__ uint32_t new_index(const LanePtrs& lp, const Flags& f
                                               uint32_t& reuse_pos, uint32_t lane) {
   if constexpr (kPlain) {
     const uint32_t b = lp.reuse[reuse_pos + 64 * C - 1];   // lane 0 of chunk 0 reads a byte it ignores
-    const uint32_t N = (C == 0 && lane == 0) ? 2u : b;
-    lp.idx[64 * C + 2] = uint8_t(N);
-    return N;
+    return (C == 0 && lane == 0) ? 2u : b;
   }
   const uint64_t inc = C == 0 ? (f.inc | 1) : f.inc;
-  const uint32_t ones = __builtin_amdgcn_mbcnt_hi(uint32_t(inc >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(inc), 0u));
-  const uint32_t fresh = ones + inc_base;
-  const uint32_t r = lp.reuse[reuse_pos - ones];
+  uint32_t fresh, r;
+  if constexpr (C == 0) {
+    // inc_base is the constant 2 here: mbcnt adds it, and the reuse rank
+    // follows from the sum (reuse_pos + 2 - fresh = reuse_pos - ones)
+    fresh = __builtin_amdgcn_mbcnt_hi(uint32_t(inc >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(inc), 2u));
+    r = lp.reuse[reuse_pos + 2 - fresh];
+  } else {
+    const uint32_t ones = __builtin_amdgcn_mbcnt_hi(uint32_t(inc >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(inc), 0u));
+    fresh = ones + inc_base;
+    r = lp.reuse[reuse_pos - ones];
+  }
   const uint32_t N = __builtin_amdgcn_inverse_ballot_w64(inc) ? fresh : r;
-  lp.idx[64 * C + 2] = uint8_t(N);
   const uint32_t news = uint32_t(__builtin_popcountll(inc));
   inc_base += news;
   reuse_pos += 64 - news;
   return N;
 }
 
-// Phase 2 for chunk C: pivot (the last L/R flip at or before t) and the
-// oriented triple, written at out_m + 3t.  In chunk 0 the change word gets
-// bit 0 set: "no flip so far" then lands on position 0, whose vertex I[0] is
-// the right pivot.
-//
-// Compacted output: only the lanes whose triple names three different
-// vertices (every triangle but the four degenerates of each restart) and
-// that lie inside the meshlet write, packed in order from kept_pos; the
-// others write to the tile's spare bytes past the longest shifted run.
-template <uint32_t C, bool kCompact, bool kPlain, uint32_t kTile>
-__device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t* idx0, uint8_t* out_m,
-                                              const Flags& f, uint32_t N, uint32_t lane, uint32_t& last_change,
-                                              uint64_t& prev_top, uint32_t T, uint32_t& kept_pos) {
+// Phase 2, reads: I[t+1] and the pivot.
+struct Pivot {
+  uint32_t P, X;
+};
+template <uint32_t C>
+__device__ __forceinline__ Pivot pivot_of(const LanePtrs& lp, const uint8_t* idx0, const Flags& f, uint32_t N,
+                                          uint32_t lane, uint32_t& last_change, uint64_t& prev_top) {
   uint64_t ch = f.lr ^ ((f.lr << 1) | prev_top);
   if (C == 0) ch |= 1;
   const uint64_t upto = ch << (63 - lane);
@@ -253,10 +253,24 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
   if (C == 0 || ch) last_change = 64 * C + 63 - uint32_t(__builtin_clzll(ch));   // else: no flip in this chunk
   prev_top = f.lr >> 63;
   // I[t+1]: the new slot of the lane below.  In a meshlet's first chunk lane 0
-  // takes I[1] = 1, so a DPP shift replaces the LDS read; later chunks read
-  // the slot their lane 0 needs from the chunk before.
-  const uint32_t P = C == 0 ? uint32_t(__builtin_amdgcn_update_dpp(1, int(N), 0x138, 0xF, 0xF, false)) : at_t[1];
-  const uint32_t X = *px;
+  // takes I[1] = 1, so a DPP shift (lane 0 gets 0, plus lane0) replaces the
+  // LDS read; later chunks read the slot their lane 0 needs from the chunk
+  // before.
+  const uint32_t P =
+      C == 0 ? uint32_t(__builtin_amdgcn_update_dpp(0, int(N), 0x138, 0xF, 0xF, true)) + lp.lane0 : at_t[1];
+  return Pivot{P, *px};
+}
+
+// Phase 2, writes: the oriented triple at out_m + 3t.
+//
+// Compacted output: only the lanes whose triple names three different
+// vertices (every triangle but the four degenerates of each restart) and
+// that lie inside the meshlet write, packed in order from kept_pos; the
+// others write to the tile's spare bytes past the longest shifted run.
+template <uint32_t C, bool kCompact, bool kPlain, uint32_t kTile>
+__device__ __forceinline__ void put_triangle(const LanePtrs& lp, uint8_t* out_m, const Flags& f, uint32_t N,
+                                             const Pivot& pv, uint32_t lane, uint32_t T, uint32_t& kept_pos) {
+  const uint32_t P = pv.P, X = pv.X;
   const bool right = __builtin_amdgcn_inverse_ballot_w64(f.lr);
   uint8_t* o;
   if constexpr (kCompact) {
@@ -271,6 +285,17 @@ __device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t*
   o[0] = uint8_t(right ? P : X);
   o[1] = uint8_t(right ? X : P);
   o[2] = uint8_t(N);
+}
+
+// Phase 2 for chunk C: the pivot (the last L/R flip at or before t; in chunk 0
+// the change word gets bit 0 set, so "no flip so far" lands on position 0,
+// whose vertex I[0] is the right pivot) and the oriented triple.
+template <uint32_t C, bool kCompact, bool kPlain, uint32_t kTile>
+__device__ __forceinline__ void emit_triangle(const LanePtrs& lp, const uint8_t* idx0, uint8_t* out_m,
+                                              const Flags& f, uint32_t N, uint32_t lane, uint32_t& last_change,
+                                              uint64_t& prev_top, uint32_t T, uint32_t& kept_pos) {
+  const Pivot pv = pivot_of<C>(lp, idx0, f, N, lane, last_change, prev_top);
+  put_triangle<C, kCompact, kPlain, kTile>(lp, out_m, f, N, pv, lane, T, kept_pos);
 }
 
 // Decodes one meshlet of NCH flag chunks (chunks co.. of the run at gb), reuse bytes
@@ -295,6 +320,10 @@ __device__ __forceinline__ void decode_meshlet(RunTile<kPlain, kTile>& tile, con
   if constexpr (NCH > 1) n1 = new_index<kPlain, 1>(lp, f1, inc_base, reuse_pos, lane);
   if constexpr (NCH > 2) n2 = new_index<kPlain, 2>(lp, f2, inc_base, reuse_pos, lane);
   if constexpr (NCH > 3) n3 = new_index<kPlain, 3>(lp, f3, inc_base, reuse_pos, lane);
+  lp.idx[2] = uint8_t(n0);
+  if constexpr (NCH > 1) lp.idx[66] = uint8_t(n1);
+  if constexpr (NCH > 2) lp.idx[130] = uint8_t(n2);
+  if constexpr (NCH > 3) lp.idx[194] = uint8_t(n3);
   wave_lds_sync();
   // lane-relative output (lp.out = tile + 3 * lane), or the tile base when compacting
   uint8_t* out_m = kCompact ? reinterpret_cast<uint8_t*>(tile.out) + ob : lp.out + ob;
@@ -304,6 +333,65 @@ __device__ __forceinline__ void decode_meshlet(RunTile<kPlain, kTile>& tile, con
   if constexpr (NCH > 1) emit_triangle<1, kCompact, kPlain, kTile>(lp, tile.idx, out_m, f1, n1, lane, last_change, prev_top, T, kept_pos);
   if constexpr (NCH > 2) emit_triangle<2, kCompact, kPlain, kTile>(lp, tile.idx, out_m, f2, n2, lane, last_change, prev_top, T, kept_pos);
   if constexpr (NCH > 3) emit_triangle<3, kCompact, kPlain, kTile>(lp, tile.idx, out_m, f3, n3, lane, last_change, prev_top, T, kept_pos);
+  wave_lds_sync();
+}
+
+// Index slots of the second meshlet of a pair start this far up the index
+// area: past the 130 slots a two-chunk meshlet uses, and with room for its
+// own 130 below the area's end.
+constexpr uint32_t kPairIdx = 136;
+
+// Two meshlets of NCH (1 or 2) chunks decoded together, so that the LDS and
+// scalar-load waits of one overlap the work of the other: the reads of both
+// phases are issued for both meshlets before either's writes.  a's chunks
+// start at run chunk co, b's at co + NCH; wa, wb: their layout words.  b's
+// index slots start kPairIdx bytes up, where the caller has set I[0] = 0 and
+// I[1] = 1.  a's triples are written before b's, so b overwrites the garbage
+// of a's lanes past its T_s.
+template <uint32_t NCH, bool kPlain, bool kCompact, uint32_t kTile>
+__device__ __forceinline__ void decode_pair(RunTile<kPlain, kTile>& tile, const LanePtrs& lp, const uint8_t* gb, uint32_t co,
+                                            uint32_t wa, uint32_t wb, uint32_t lane, uint32_t Ta, uint32_t Tb) {
+  static_assert(NCH == 1 || NCH == 2, "pairs of one- or two-chunk meshlets");
+  static_assert(kPairIdx >= 64 * NCH + 2 && kPairIdx + 64 * NCH + 2 <= sizeof(RunTile<kPlain, kTile>::idx), "index area");
+  LanePtrs lq = lp;
+  lq.idx += kPairIdx;
+  const Flags fa0 = chunk_flags<kPlain>(gb, co), fb0 = chunk_flags<kPlain>(gb, co + NCH);
+  Flags fa1{0, 0}, fb1{0, 0};
+  if constexpr (NCH > 1) {
+    fa1 = chunk_flags<kPlain>(gb, co + 1);
+    fb1 = chunk_flags<kPlain>(gb, co + 3);
+  }
+  uint32_t ia = 2, ib = 2, ra = (wa >> 6) & 2047u, rb = (wb >> 6) & 2047u;
+  const uint32_t na0 = new_index<kPlain, 0>(lp, fa0, ia, ra, lane);
+  const uint32_t nb0 = new_index<kPlain, 0>(lq, fb0, ib, rb, lane);
+  uint32_t na1 = 0, nb1 = 0;
+  if constexpr (NCH > 1) {
+    na1 = new_index<kPlain, 1>(lp, fa1, ia, ra, lane);
+    nb1 = new_index<kPlain, 1>(lq, fb1, ib, rb, lane);
+  }
+  lp.idx[2] = uint8_t(na0);
+  lq.idx[2] = uint8_t(nb0);
+  if constexpr (NCH > 1) {
+    lp.idx[66] = uint8_t(na1);
+    lq.idx[66] = uint8_t(nb1);
+  }
+  wave_lds_sync();
+  uint32_t lca = 0, lcb = 0, ka = 0, kb = 0;
+  uint64_t pta = 0, ptb = 0;
+  const Pivot pa0 = pivot_of<0>(lp, tile.idx, fa0, na0, lane, lca, pta);
+  const Pivot pb0 = pivot_of<0>(lq, tile.idx + kPairIdx, fb0, nb0, lane, lcb, ptb);
+  Pivot pa1{0, 0}, pb1{0, 0};
+  if constexpr (NCH > 1) {
+    pa1 = pivot_of<1>(lp, tile.idx, fa1, na1, lane, lca, pta);
+    pb1 = pivot_of<1>(lq, tile.idx + kPairIdx, fb1, nb1, lane, lcb, ptb);
+  }
+  uint8_t* const base = kCompact ? reinterpret_cast<uint8_t*>(tile.out) : lp.out;
+  uint8_t* const out_a = base + ((wa >> 17) & 4095u);
+  uint8_t* const out_b = base + ((wb >> 17) & 4095u);
+  put_triangle<0, kCompact, kPlain, kTile>(lp, out_a, fa0, na0, pa0, lane, Ta, ka);
+  if constexpr (NCH > 1) put_triangle<1, kCompact, kPlain, kTile>(lp, out_a, fa1, na1, pa1, lane, Ta, ka);
+  put_triangle<0, kCompact, kPlain, kTile>(lp, out_b, fb0, nb0, pb0, lane, Tb, kb);
+  if constexpr (NCH > 1) put_triangle<1, kCompact, kPlain, kTile>(lp, out_b, fb1, nb1, pb1, lane, Tb, kb);
   wave_lds_sync();
 }
 
@@ -433,10 +521,29 @@ __device__ __forceinline__ uint4 load_reuse(const Stream& s, const Plan& p, uint
 }
 
 // A run whose k meshlets all have NCH chunks: meshlet i's chunks start at
-// chunk NCH * i of the run, and no meshlet needs a size dispatch.
+// chunk NCH * i of the run, and no meshlet needs a size dispatch.  Meshlets
+// of up to kPairMaxChunks chunks are decoded in pairs (a run's odd last one
+// alone).
+constexpr uint32_t kPairMaxChunks = 2;
 template <uint32_t NCH, bool kPlain, bool kCompact, uint32_t kTile>
 __device__ __forceinline__ void decode_run_same(RunTile<kPlain, kTile>& tile, const LanePtrs& lp, uint32_t k, uint32_t layout,
                                                 uint32_t tri_counts, const uint8_t* gb, uint32_t lane) {
+  if constexpr (NCH <= kPairMaxChunks) {
+    if (lane < 2) tile.idx[kPairIdx + lane] = uint8_t(lane);
+    uint32_t i = 0;
+    for (; i + 1 < k; i += 2) {
+      const uint32_t wa = lane_value(layout, i), wb = lane_value(layout, i + 1);
+      const uint32_t Ta = kCompact ? lane_value(tri_counts, i) : 0u;
+      const uint32_t Tb = kCompact ? lane_value(tri_counts, i + 1) : 0u;
+      decode_pair<NCH, kPlain, kCompact, kTile>(tile, lp, gb, NCH * i, wa, wb, lane, Ta, Tb);
+    }
+    if (i < k) {
+      const uint32_t w = lane_value(layout, i);
+      const uint32_t T = kCompact ? lane_value(tri_counts, i) : 0u;
+      decode_meshlet<NCH, kPlain, kCompact, kTile>(tile, lp, gb, NCH * i, (w >> 6) & 2047u, (w >> 17) & 4095u, lane, T);
+    }
+    return;
+  }
   for (uint32_t i = 0; i < k; ++i) {
     const uint32_t w = lane_value(layout, i);
     const uint32_t T = kCompact ? lane_value(tri_counts, i) : 0u;
@@ -585,6 +692,7 @@ __device__ __forceinline__ RunTile<kPlain, kTile>& wave_tile(uint32_t wave, uint
   lp.reuse = tile.reuse + lane;
   lp.idx = tile.idx + lane;
   lp.out = reinterpret_cast<uint8_t*>(tile.out) + 3 * lane;
+  lp.lane0 = lane == 0 ? 1u : 0u;
   return tile;
 }
 
@@ -733,14 +841,15 @@ int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gts
     return fail(GTSR_EINVAL, std::string(who) + ": tables must be 16-byte aligned");
   Defaults d;
   // measured best on the batched 2000-mesh workload: one-wave groups, 256 per
-  // CU (8 times the resident count, so freed slots are refilled until the end)
+  // CU (about 9 times the resident count, so freed slots are refilled until
+  // the end)
   d.waves = 1;
   d.gpc = 256;
   if (int rc = resolve_cfg(cfg, d, who, true, plain)) return rc;
   const uint32_t cus = cu_count();
   if (!cus) return fail(GTSR_EHIP, std::string(who) + ": cannot query the device");
   if (work_items == 0) return ok();
-  // resident grid, or fewer groups when the list has fewer items than that grid has wavefronts
+  // the configured grid, or fewer groups when the list has fewer items than that grid has wavefronts
   const uint64_t want = (uint64_t(work_items) + d.waves - 1) / d.waves;
   const uint32_t groups = round_up8(std::min<uint64_t>(uint64_t(cus) * d.gpc, want));
   if (plain)
