@@ -328,6 +328,25 @@ def test_compact_encoded_meshes_both_formats(name, caps):
     assert_compact_parity(P.to_device(P.gts_from_reuse(sl)), full, sl.desc_bytes, CFGS[:1], f"{name} {caps}")
 
 
+@pytest.mark.parametrize("nch", [1, 2, 3, 4])
+def test_uniform_chunk_count_runs(nch):
+    """Streams whose meshlets all span nch flag chunks: every run takes the
+    loop specialised to one chunk count, and one- and two-chunk meshlets are
+    decoded several at a time.  Waves of 1, 2, 3, 5, 7 and 64 meshlets give
+    runs of odd and even lengths, so every group size and the odd meshlet
+    left over are covered; both formats and the compacted output."""
+    rng = np.random.default_rng(700 + nch)
+    lo, hi = 64 * (nch - 1) + 1, 64 * nch
+    ms = [random_stream(rng, int(rng.integers(lo, hi + 1)), float(rng.uniform(0.05, 0.95)),
+                        float(rng.uniform(0.02, 0.98))) for _ in range(613)]
+    desc, bits, reuse, ts = pack(ms)
+    cfgs = [None] + [{"waves_per_group": 2, "meshlets_per_wave": k} for k in (1, 2, 3, 5, 7, 64)]
+    assert_parity(desc, bits, reuse, ts, cfgs, f"uniform nch={nch}")
+    assert_gts_parity(O.gts_from_reuse(desc, bits, reuse, ts), cfgs[:4], f"uniform nch={nch}")
+    full = O.decode_arrays(desc, bits, reuse, ts)
+    assert_compact_parity(device_stream(desc, bits, reuse, ts), full, desc, cfgs[:4], f"uniform nch={nch}")
+
+
 def test_compact_output_too_small_skips_tail_meshlets():
     m = meshgen.workload1()
     sl = P.encode(m.tri, m.nverts, 64, 126)
