@@ -371,7 +371,8 @@ typedef struct gtsr_server gtsr_server;   /* opaque */
 
 typedef struct gtsr_server_params {
   uint8_t* arena;            /* device memory for decoded outputs, caller-owned, 256-byte aligned */
-  uint64_t arena_bytes;      /* the admission budget for outputs in flight or unreleased */
+  uint64_t arena_bytes;      /* the admission budget for outputs in flight or unreleased; each
+                                output takes whole 256-byte units of it */
   uint32_t max_inflight;     /* batches on the device at once, 1..8 (0 = 4) */
   uint32_t max_batch;        /* requests per batch, 1..65536 (0 = 256) */
   uint32_t target_tris;      /* strip triangles per work item (0 = 768) */
@@ -413,8 +414,8 @@ int gtsr_server_create(const gtsr_mesh_entry* host_table, const gtsr_meshlet* co
 
 /* Queue a decode of mesh under a caller-chosen tag, unique among the
  * requests not yet released.  Thread-safe, returns at once.  Errors: EINVAL
- * (mesh out of range, tag in use), ELIMIT (the output can never fit the
- * arena). */
+ * (mesh out of range, tag in use), ELIMIT (the output, rounded up to whole
+ * 256-byte units, can never fit the arena). */
 int gtsr_server_submit(gtsr_server* server, uint32_t mesh, uint64_t tag);
 
 /* Move up to capacity finished requests to out (oldest first) and their number

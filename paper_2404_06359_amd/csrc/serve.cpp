@@ -37,6 +37,11 @@ namespace {
 
 constexpr uint64_t kArenaAlign = 256;
 
+// Arena bytes an output of `bytes` occupies (whole 256-byte units, at least one).
+uint64_t arena_span(uint64_t bytes) {
+  return std::max<uint64_t>(kArenaAlign, (bytes + kArenaAlign - 1) / kArenaAlign * kArenaAlign);
+}
+
 uint64_t now_ns() {
   return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(
                       std::chrono::steady_clock::now().time_since_epoch())
@@ -50,7 +55,7 @@ class Arena {
     if (size) free_[0] = size;
   }
   bool alloc(uint64_t bytes, uint64_t& off) {
-    bytes = std::max<uint64_t>(kArenaAlign, (bytes + kArenaAlign - 1) / kArenaAlign * kArenaAlign);
+    bytes = arena_span(bytes);
     for (auto it = free_.begin(); it != free_.end(); ++it) {
       if (it->second >= bytes) {
         off = it->first;
@@ -64,7 +69,7 @@ class Arena {
     return false;
   }
   void release(uint64_t off, uint64_t bytes) {
-    bytes = std::max<uint64_t>(kArenaAlign, (bytes + kArenaAlign - 1) / kArenaAlign * kArenaAlign);
+    bytes = arena_span(bytes);
     used_ -= bytes;
     auto it = free_.emplace(off, bytes).first;
     auto next = std::next(it);
@@ -384,7 +389,9 @@ extern "C" int gtsr_server_submit(gtsr_server* s, uint32_t mesh, uint64_t tag) {
   if (!s) return fail(GTSR_EINVAL, "gtsr_server_submit: null server");
   if (mesh >= s->meshes.size()) return fail(GTSR_EINVAL, "gtsr_server_submit: mesh out of range");
   const MeshInfo& mi = s->meshes[mesh];
-  if (mi.out_bytes > s->arena.size())
+  // (checked in the arena's 256-byte units: an output that fits only unrounded
+  // could never be admitted and would block every request behind it)
+  if (mi.out_bytes && arena_span(mi.out_bytes) > s->arena.size())
     return fail(GTSR_ELIMIT, "gtsr_server_submit: the mesh's output is larger than the arena");
   if (mi.cuts.size() - 1 > s->p.max_items)
     return fail(GTSR_ELIMIT, "gtsr_server_submit: the mesh needs more work items than a batch holds");

@@ -128,3 +128,22 @@ def test_server_errors(pool):
     out = drain(srv, 1)
     np.testing.assert_array_equal(out[7], refs[i])
     srv.close()
+
+
+def test_server_arena_units(pool):
+    """An output takes whole 256-byte units of the arena: a mesh whose output
+    fits the arena only unrounded is refused at submit, not queued for ever
+    (it would block every request behind it)."""
+    pool_, refs = pool
+    i = len(refs) - 1                    # the one-triangle fan: 3 output bytes
+    assert refs[i].nbytes == 3
+    srv = P.Server(pool_, arena_bytes=255, max_inflight=1)
+    with pytest.raises(P.GtsrError) as e:
+        srv.submit(i, 1)
+    assert e.value.code == P.ELIMIT
+    srv.close()
+    srv = P.Server(pool_, arena_bytes=256, max_inflight=1)
+    srv.submit(i, 1)
+    out = drain(srv, 1)
+    np.testing.assert_array_equal(out[1], refs[i])
+    srv.close()
