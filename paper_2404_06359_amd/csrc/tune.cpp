@@ -1,10 +1,11 @@
 // Launch-shape autotuner for the batched decoder (host code, HIP runtime API).
 //
-// The batched decoder's speed depends on three knobs the stream format leaves
+// The batched decoder's speed depends on four knobs the stream format leaves
 // open: how many strip triangles one work item holds (gtsr_plan_batch's
 // target, i.e. how many meshlets a wavefront takes per item), how many
-// wavefronts share a workgroup, and how many workgroups the persistent grid
-// keeps on each CU.  gtsr_autotune_batched measures every requested
+// wavefronts share a workgroup, how many workgroups the grid holds per CU,
+// and the LDS tile (the longest run of strip triangles a wavefront stages at
+// once).  gtsr_autotune_batched measures every requested
 // combination on the caller's own meshes and returns the fastest.  Every
 // candidate decodes the whole table into its outputs, so the outputs hold the
 // decoded meshes afterwards, exactly as after one decode_meshlets_batched.
@@ -21,8 +22,8 @@ using namespace gtsr;
 namespace {
 
 const uint32_t kDefaultTargets[] = {384, 768, 1536, 3072};
-// Resident grids (32 waves per CU) and grids 4 and 8 times larger, which the
-// dispatcher refills as groups finish, each with both LDS tiles (1280- and
+// Grids of 32 waves per CU and grids 4 and 8 times larger (the dispatcher
+// refills freed slots as groups finish), each with both LDS tiles (1280- and
 // 1024-triangle runs).
 const gtsr_launch_cfg kDefaultCfgs[] = {
     {1, 0, 32, 1280}, {2, 0, 16, 1280}, {1, 0, 128, 1280}, {1, 0, 256, 1280}, {2, 0, 64, 1280},
