@@ -158,7 +158,12 @@ typedef struct gtsr_mesh_entry {
   uint64_t strip_triangles;
 } gtsr_mesh_entry;
 
-/* One work item of the batched decoder: meshlets [first, end) of one mesh. */
+/* One work item of the batched decoder: meshlets [first, end) of one mesh.
+ * An item past the mesh's meshlet count is clipped to it, one with
+ * first >= end decodes nothing, and overlapping items decode the shared
+ * meshlets again (the same bytes).  Consecutive items of one mesh where the
+ * second starts at the first's end are decoded as one range [first of the
+ * first, end of the last). */
 typedef struct gtsr_work_item {
   uint32_t mesh;
   uint32_t first;
@@ -298,7 +303,7 @@ int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_ou
  * meshlets, bits and reuse pointer (entries that are not are skipped); each
  * reuse allocation must extend to a multiple of 16 bytes, and no entry's
  * sizes may exceed its allocations (as for decode_meshlets).  The grid holds groups_per_cu groups per CU (default: 256
- * one-wavefront groups, eight times what stays resident, so the dispatcher
+ * one-wavefront groups, about nine times what stays resident, so the dispatcher
  * refills freed slots until the work runs out; fewer groups when the list has
  * fewer items than that grid has wavefronts); each wavefront decodes one contiguous block of the work list,
  * so the list should be balanced by strip triangles (gtsr_plan_batch) and

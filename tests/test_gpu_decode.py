@@ -187,6 +187,41 @@ def test_batched_persistent(target):
             np.testing.assert_array_equal(o.cpu().numpy(), ref)
 
 
+def test_batched_irregular_work_lists():
+    """Work lists the planner never writes: one-meshlet items in shuffled
+    order, overlapping items, an empty and a reversed item, an item past its
+    mesh's end (clipped), items naming a mesh past the table (skipped), and a
+    table entry with a misaligned array (skipped: its output stays as it was).
+    Every decoded mesh equals the oracle."""
+    meshes = _batched_meshes()[:5]
+    encs = [O.encode(m.tri, m.nverts, *caps) for m, caps in meshes]
+    refs = [O.decode(s) for s in encs]
+    streams = [device_stream(s.desc, s.bits, s.reuse, s.strip_triangles) for s in encs]
+    b = P.Batch(streams, target_tris=768, host_meshlets=[s.desc.view(P.MESHLET_DTYPE) for s in encs])
+    table = b.table.cpu().numpy().view(P.MESH_ENTRY_DTYPE).copy()
+    table[4]["meshlets"] += 4
+    dtable = torch.from_numpy(table.view(np.uint8).reshape(-1).copy()).cuda()
+    M = [s.desc.size // 16 for s in encs]
+    items = [(0, i, i + 1, 0) for i in range(M[0])]
+    items += [(1, 0, M[1] // 2 + 3, 0), (1, M[1] // 2, M[1] + 1000, 0)]
+    items += [(2, 5, 5, 0), (2, 0xFFFFFF00, 3, 0), (2, 0, M[2], 0)]
+    items += [(3, 0, M[3], 0), (99, 0, 10, 0), (5, 0, 1, 0)]
+    items += [(4, 0, M[4], 0)]
+    order = np.random.default_rng(11).permutation(len(items))
+    work = np.array([items[i] for i in order], dtype=np.uint32).reshape(-1)
+    dwork = torch.from_numpy(work.view(np.uint8).copy()).cuda()
+    n_items = len(items)
+    for cfg in (None, {"waves_per_group": 1, "groups_per_cu": 1}, {"waves_per_group": 4, "groups_per_cu": 2}):
+        say(f"[gpu] irregular work list cfg={cfg} items={n_items}")
+        b.out_all.fill_(0xAA)
+        P._check(P.lib().decode_meshlets_batched(dtable.data_ptr(), 5, dwork.data_ptr(), n_items, P._cfg(cfg),
+                                                 P._stream_handle(None)))
+        torch.cuda.synchronize()
+        for i in range(4):
+            np.testing.assert_array_equal(b.outs[i].cpu().numpy(), refs[i], err_msg=f"mesh {i}")
+        assert (b.outs[4].cpu().numpy() == 0xAA).all()
+
+
 def test_batched_graph_replays():
     encs = [O.encode(m.tri, m.nverts, *caps) for m, caps in _batched_meshes()]
     refs = [O.decode(s) for s in encs]
