@@ -139,6 +139,35 @@ def test_library_stream_equals_oracle_stream_and_decodes():
     np.testing.assert_array_equal(O.round_trip_triangles(so, got), O.canonical(m.tri))
 
 
+def test_corrupt_descriptors_are_skipped():
+    """Descriptors with counts out of range or offsets past the arrays are
+    skipped: their output bytes stay as they were, and every other meshlet,
+    including the one after each bad descriptor (which then starts a run of
+    its own), equals the oracle."""
+    m = MESHES["sphere5"]()
+    st = O.encode(m.tri, m.nverts, 64, 126)
+    ref = O.decode(st).copy()
+    d = st.desc.view(P.MESHLET_DTYPE).copy()
+    M = d.size
+    nchunks = st.bits.size // 16
+    bad = {5: ("tri_count", 0), 17: ("tri_count", 300), 40: ("vert_count", 2),
+           41: ("vert_count", 200), 77: ("chunk_off", nchunks), 78: ("reuse_off", st.reuse.size + 1),
+           123: ("out_off", st.strip_triangles), M - 1: ("chunk_off", 0xFFFFFFF0)}
+    for i, (field, value) in bad.items():
+        a, t = int(d[i]["out_off"]), int(d[i]["tri_count"])
+        if field == "vert_count" and value == 200:
+            value = t + 3                       # more vertices than index slots
+        d[i][field] = value
+        ref[a:a + t] = 0xAA
+    desc = d.view(np.uint8)
+    for cfg in CFGS[:3]:
+        say(f"[gpu] corrupt descriptors cfg={cfg} meshlets={M}")
+        got = gpu_decode(desc, st.bits, st.reuse, st.strip_triangles, cfg, 0xAA)
+        if not np.array_equal(got, ref):
+            rows = np.nonzero((got != ref).any(axis=1))[0]
+            pytest.fail(f"cfg={cfg}: {rows.size} triangles differ, first {rows[:5]}")
+
+
 def test_empty_stream():
     ds = device_stream(np.zeros(0, np.uint8), np.zeros(0, np.uint8), np.zeros(0, np.uint8), 0)
     out = P.decode(ds)
