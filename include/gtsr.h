@@ -342,9 +342,9 @@ typedef struct gtsr_tune_point {
  * For every target in targets[n_targets] (strip triangles per work item,
  * i.e. meshlets per wavefront step; NULL or 0 = 384, 768, 1536, 3072) the
  * work list is planned as gtsr_plan_batch does, and for every shape in
- * cfgs[n_cfgs] (NULL or 0 = seven waves-per-group x groups-per-CU pairs: 32
- * resident wavefronts per CU, and grids 4 and 8 times that, each with
- * run_tris 1280 and 1024: fourteen shapes) one warm-up and
+ * cfgs[n_cfgs] (NULL or 0 = nine waves-per-group x groups-per-CU pairs: 32
+ * wavefronts per CU, and grids 4, 8 and 16 times that, each with run_tris
+ * 1280 and 1024: eighteen shapes) one warm-up and
  * reps timed launches
  * (0 = 5, at most 1000) of decode_meshlets_batched run on hip_stream, each
  * timed with HIP events.  *best receives the point with the lowest median;

@@ -606,7 +606,7 @@ class Pool:
         for i, c in enumerate(cfgs or []):
             cf[i] = LaunchCfg(int(c.get("waves_per_group", 0)), 0, int(c.get("groups_per_cu", 0)),
                               int(c.get("run_tris", 0)))
-        cap = max(1, len(tg) or 4) * max(1, len(cfgs or []) or 14)
+        cap = max(1, len(tg) or 4) * max(1, len(cfgs or []) or 18)
         pts = (TunePoint * cap)()
         cnt = C.c_uint32()
         best = TunePoint()

@@ -22,13 +22,14 @@ using namespace gtsr;
 namespace {
 
 const uint32_t kDefaultTargets[] = {384, 768, 1536, 3072};
-// Grids of 32 waves per CU and grids 4 and 8 times larger (the dispatcher
-// refills freed slots as groups finish), each with both LDS tiles (1280- and
-// 1024-triangle runs).
+// Grids of 32 waves per CU and grids 4, 8 and 16 times larger (the
+// dispatcher refills freed slots as groups finish), each with both LDS tiles
+// (1280- and 1024-triangle runs).
 const gtsr_launch_cfg kDefaultCfgs[] = {
-    {1, 0, 32, 1280}, {2, 0, 16, 1280}, {1, 0, 128, 1280}, {1, 0, 256, 1280}, {2, 0, 64, 1280},
-    {2, 0, 128, 1280}, {4, 0, 32, 1280}, {1, 0, 32, 1024}, {2, 0, 16, 1024}, {1, 0, 128, 1024},
-    {1, 0, 256, 1024}, {2, 0, 64, 1024}, {2, 0, 128, 1024}, {4, 0, 32, 1024},
+    {1, 0, 32, 1280},  {2, 0, 16, 1280},  {1, 0, 128, 1280}, {1, 0, 256, 1280}, {2, 0, 64, 1280},
+    {2, 0, 128, 1280}, {4, 0, 32, 1280},  {1, 0, 512, 1280}, {2, 0, 256, 1280}, {1, 0, 32, 1024},
+    {2, 0, 16, 1024},  {1, 0, 128, 1024}, {1, 0, 256, 1024}, {2, 0, 64, 1024},  {2, 0, 128, 1024},
+    {4, 0, 32, 1024},  {1, 0, 512, 1024}, {2, 0, 256, 1024},
 };
 
 struct Events {
