@@ -347,8 +347,8 @@ def cpu_baseline(encs, pool, threads):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", choices=["batched", "sphere", "serve", "gts", "compact", "cull", "dequant"],
                     default="batched")
     ap.add_argument("--pool-meshes", type=int, default=5000, help="serve: pool size")
