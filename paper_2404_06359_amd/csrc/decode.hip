@@ -699,14 +699,17 @@ __device__ __forceinline__ RunTile<kPlain, kTile>& wave_tile(uint32_t wave, uint
 // Splits [0, n) into one contiguous block per wavefront of the grid, XCD-major:
 // workgroups are dispatched round-robin over the 8 XCDs, so the blocks of one
 // XCD's waves are adjacent and its L2 sees whole output lines.
-__device__ __forceinline__ void wave_block(uint64_t n, uint32_t wave, uint32_t waves, uint64_t& b0, uint64_t& b1) {
+__device__ __forceinline__ void wave_block(uint32_t n, uint32_t wave, uint32_t waves, uint32_t& b0, uint32_t& b1) {
   const uint32_t xcd = blockIdx.x % kXcds;
-  const uint32_t per_xcd = gridDim.x / kXcds;             // the grid is a multiple of 8
-  const uint64_t wx = uint64_t(per_xcd) * waves;          // waves of this XCD
-  const uint64_t q = uint64_t(blockIdx.x / kXcds) * waves + wave;
-  const uint64_t x0 = n * xcd / kXcds, x1 = n * (xcd + 1) / kXcds;
-  b0 = x0 + (x1 - x0) * q / wx;
-  b1 = x0 + (x1 - x0) * (q + 1) / wx;
+  const uint32_t wx = gridDim.x / kXcds * waves;            // waves of this XCD (the grid is a multiple of 8)
+  const uint32_t q = blockIdx.x / kXcds * waves + wave;     // this wave's rank among them
+  const uint32_t x0 = uint32_t(uint64_t(n) * xcd / kXcds), x1 = uint32_t(uint64_t(n) * (xcd + 1) / kXcds);
+  // equal shares, one more for the first (x1 - x0) mod wx waves: one 32-bit
+  // division (two 64-bit ones cost every wave of the grid ~230 scalar
+  // instructions); q < wx, so the clamps only guard
+  const uint32_t len = x1 - x0, share = len / wx, extra = len % wx;
+  b0 = min(x0 + q * share + min(q, extra), x1);
+  b1 = min(b0 + share + (q < extra ? 1u : 0u), x1);
 }
 
 // Plain decoder: every wavefront decodes one contiguous block of meshlets.
@@ -723,12 +726,12 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
   const uint32_t wave = uniform(threadIdx.x / kWave);
   LanePtrs lp;
   RunTile<kPlain, kTile>& tile = wave_tile<kPlain, kTile>(wave, lane, lp);
-  uint64_t b0, b1;
+  uint32_t b0, b1;
   wave_block(meshlet_count, wave, blockDim.x / kWave, b0, b1);
   if (b0 >= b1) return;
   const Stream s{reinterpret_cast<const uint8_t*>(meshlets), bits, reuse, out, kept,
                  clip32(chunks), clip32(reuse_bytes), clip32(out_tris), meshlet_count, cones, {vx, vy, vz}};
-  decode_range<kPlain, kCompact, kCull, kTile>(s, uint32_t(b0), uint32_t(b1), tile, lp, lane);
+  decode_range<kPlain, kCompact, kCull, kTile>(s, b0, b1, tile, lp, lane);
 }
 
 // Persistent batched decoder: every wavefront takes one contiguous block of
@@ -743,7 +746,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
   const uint32_t wave = uniform(threadIdx.x / kWave);
   LanePtrs lp;
   RunTile<kPlain, kTile>& tile = wave_tile<kPlain, kTile>(wave, lane, lp);
-  uint64_t b0, b1;
+  uint32_t b0, b1;
   wave_block(work_items, wave, blockDim.x / kWave, b0, b1);
   for (uint64_t base = b0; base < b1; base += kWave) {
     const uint32_t cnt = uint32_t(min(b1 - base, uint64_t(kWave)));
