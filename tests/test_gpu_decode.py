@@ -65,6 +65,21 @@ def test_exhaustive_small_streams():
     assert_parity(desc, bits, reuse, ts, CFGS, "exhaustive T_s<=6")
 
 
+def test_exhaustive_seven_triangle_streams_one_launch():
+    """Every stream with T_s = 7 (1,341,568 meshlets: all flags, all
+    increment patterns, every admissible reuse value) decoded by one launch,
+    in the default shape and with one meshlet per wavefront."""
+    ms = list(all_streams(7))
+    desc, bits, reuse, ts = pack(ms)
+    ref = O.decode_arrays(desc, bits, reuse, ts)
+    for cfg in (None, {"waves_per_group": 4, "meshlets_per_wave": 1}):
+        say(f"[gpu] exhaustive T_s=7 cfg={cfg} meshlets={desc.size // 16}")
+        got = gpu_decode(desc, bits, reuse, ts, cfg, 0xAA)
+        if not np.array_equal(got, ref):
+            rows = np.nonzero((got != ref).any(axis=1))[0]
+            pytest.fail(f"T_s=7 cfg={cfg}: {rows.size} triangles differ, first {rows[:5]}")
+
+
 def test_random_long_streams():
     rng = np.random.default_rng(2024)
     ms = []
