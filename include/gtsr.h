@@ -142,7 +142,17 @@ typedef struct gtsr_launch_cfg {
   uint32_t run_tris;            /* batched decoders: the LDS tile, as strip triangles per run:
                                    0 = default, 1280 or 1024 (GTS-Reuse), 1024 (plain GTS);
                                    every other decoder: must be 0 */
+  uint32_t items_per_claim;     /* batched decoders: 0 = static split (each wavefront of an
+                                   over-subscribed grid decodes one block of the work list);
+                                   1..1024 = persistent grid (groups_per_cu groups per CU, at
+                                   most one wavefront per claim) whose wavefronts claim this
+                                   many work items at a time from per-XCD counters kept in
+                                   the caller's workspace; every other decoder: must be 0 */
 } gtsr_launch_cfg;
+
+/* Workspace bytes a batched decode with cfg.items_per_claim > 0 needs: eight
+ * 32-bit counters, one per 128-byte line. */
+#define GTSR_BATCHED_WORKSPACE_BYTES 1024u
 
 /* One row of the batched decoder's mesh table (device memory, 64 bytes):
  * a gtsr_stream's device pointers plus where its output goes. */
@@ -297,67 +307,101 @@ int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_ou
                               const uint64_t* out_bytes, uint32_t n, const gtsr_launch_cfg* cfg,
                               void* hip_stream);
 
-/* Decode many meshes in one persistent launch.  dev_mesh_table: device
+/* Decode many meshes in one launch.  dev_mesh_table: device
  * gtsr_mesh_entry[mesh_count]; dev_work: device gtsr_work_item[work_items]
  * (gtsr_plan_batch); both 16-byte aligned, as must be every entry's
  * meshlets, bits and reuse pointer (entries that are not are skipped); each
  * reuse allocation must extend to a multiple of 16 bytes, and no entry's
- * sizes may exceed its allocations (as for decode_meshlets).  The grid holds groups_per_cu groups per CU (default: 256
- * one-wavefront groups, about nine times what stays resident, so the dispatcher
- * refills freed slots until the work runs out; fewer groups when the list has
- * fewer items than that grid has wavefronts); each wavefront decodes one contiguous block of the work list,
- * so the list should be balanced by strip triangles (gtsr_plan_batch) and
- * have many more items than the grid has wavefronts.  No atomics, no
- * scratch memory.  Same skipping rule as decode_meshlets; items naming a
- * mesh >= mesh_count are skipped.  Errors: EINVAL, EHIP. */
+ * sizes may exceed its allocations (as for decode_meshlets).  Two launch
+ * modes (cfg->items_per_claim):
+ *   0 (default): static split.  The grid holds groups_per_cu groups per CU
+ *     (default: 256 one-wavefront groups, about nine times what stays
+ *     resident, so the dispatcher refills freed slots until the work runs
+ *     out; fewer groups when the list has fewer items than that grid has
+ *     wavefronts); each wavefront decodes one contiguous block of the work
+ *     list and exits.  No atomics; dev_workspace may be NULL.
+ *   k > 0: persistent.  The grid holds groups_per_cu groups per CU (meant
+ *     to be about the resident count, e.g. 32 one-wavefront groups), and
+ *     each wavefront claims k consecutive items at a time from a counter of
+ *     its XCD's eighth of the list until that eighth runs out.  The counters
+ *     live in dev_workspace (device, 4-byte aligned, at least
+ *     GTSR_BATCHED_WORKSPACE_BYTES bytes, caller-owned) and are zeroed by a
+ *     small kernel enqueued in front of the decode, so calls that share a
+ *     workspace must not overlap (one stream, or ordered streams).
+ * The list should be balanced by strip triangles (gtsr_plan_batch) and have
+ * many more items than the grid has wavefronts.  Same skipping rule as
+ * decode_meshlets; items naming a mesh >= mesh_count are skipped.  Enqueued
+ * on hip_stream; allocates nothing.  Errors: EINVAL (null or misaligned
+ * pointer, bad cfg, workspace missing or too small for claiming, more than
+ * 2^31 work items), EHIP. */
 int decode_meshlets_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
-                            const gtsr_work_item* dev_work, uint32_t work_items,
-                            const gtsr_launch_cfg* cfg, void* hip_stream);
+                            const gtsr_work_item* dev_work, uint32_t work_items, void* dev_workspace,
+                            uint64_t workspace_bytes, const gtsr_launch_cfg* cfg, void* hip_stream);
 
 /* decode_meshlets_batched for a table whose entries all hold plain GTS
  * streams (bits = L/R words, bits_bytes a multiple of 8; reuse = index
  * bytes). */
 int gtsr_decode_gts_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
-                            const gtsr_work_item* dev_work, uint32_t work_items,
-                            const gtsr_launch_cfg* cfg, void* hip_stream);
+                            const gtsr_work_item* dev_work, uint32_t work_items, void* dev_workspace,
+                            uint64_t workspace_bytes, const gtsr_launch_cfg* cfg, void* hip_stream);
 
-/* Capture decode_meshlets_batched into an executable HIP graph once;
- * *graph_exec receives the handle.  The tables must stay valid while the
- * graph is used; their contents may change between launches, their
- * addresses and sizes may not.  Errors: EINVAL, EHIP. */
+/* Capture one batched decode into an executable HIP graph once (its kernel
+ * node, and with cfg->items_per_claim > 0 the counter-zeroing kernel node in
+ * front of it); *graph_exec receives the handle.  format: GTSR_FORMAT_REUSE
+ * (decode_meshlets_batched) or GTSR_FORMAT_GTS (gtsr_decode_gts_batched);
+ * workspace as for those.  Captured on a stream of the library's own, so
+ * the graph has no upstream dependency on the caller's stream: the launch
+ * takes its stream in gtsr_graph_launch instead of here.  The tables and
+ * the workspace must stay valid while the graph is used; their contents may
+ * change between launches, their addresses and sizes may not.  Errors:
+ * EINVAL, EHIP. */
 int gtsr_batched_graph_create(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
-                              const gtsr_work_item* dev_work, uint32_t work_items,
-                              const gtsr_launch_cfg* cfg, void** graph_exec);
+                              const gtsr_work_item* dev_work, uint32_t work_items, void* dev_workspace,
+                              uint64_t workspace_bytes, uint32_t format, const gtsr_launch_cfg* cfg,
+                              void** graph_exec);
 
-/* One measured launch shape of gtsr_autotune_batched (32 bytes). */
+/* One measured launch shape of gtsr_autotune_batched (44 bytes). */
 typedef struct gtsr_tune_point {
-  uint32_t target_tris;       /* gtsr_plan_batch target the work list was built with */
+  uint32_t target_tris;       /* gtsr_autotune_batched: index of the candidate work list */
   uint32_t work_items;        /* items in that work list */
-  gtsr_launch_cfg cfg;        /* waves_per_group, groups_per_cu, run_tris (meshlets_per_wave unused) */
-  float median_ms, min_ms;    /* over the timed launches */
+  gtsr_launch_cfg cfg;        /* waves_per_group, groups_per_cu, run_tris, items_per_claim */
+  float median_ms, min_ms;    /* per launch, over the rounds of the last stage that measured it */
+  uint32_t stage;             /* 1, or 2 for a finalist (measured again alone) */
+  uint32_t reserved;
 } gtsr_tune_point;
 
-/* Pick the batched decoder's launch shape and LDS tile by measurement (the
- * paper decodes one meshlet per workgroup and has no such knob).
- * For every target in targets[n_targets] (strip triangles per work item,
- * i.e. meshlets per wavefront step; NULL or 0 = 384, 768, 1536, 3072) the
- * work list is planned as gtsr_plan_batch does, and for every shape in
- * cfgs[n_cfgs] (NULL or 0 = nine waves-per-group x groups-per-CU pairs: 32
- * wavefronts per CU, and grids 4, 8 and 16 times that, each with run_tris
- * 1280 and 1024: eighteen shapes) one warm-up and
- * reps timed launches
- * (0 = 5, at most 1000) of decode_meshlets_batched run on hip_stream, each
- * timed with HIP events.  *best receives the point with the lowest median;
- * points (may be NULL) receives up to capacity points in measurement order
- * and *point_count (may be NULL) the number measured.  host_meshlets and
- * meshlet_counts describe the same meshes as dev_mesh_table (as for
- * gtsr_plan_batch).  Synchronous: returns after the last timed launch.  It
- * allocates one device work list for its own use and frees it.  Every launch
- * decodes the whole table, so the table's outputs hold the decoded meshes on
- * return.  Errors: EINVAL (null argument, target 0, bad cfg), EHIP. */
-int gtsr_autotune_batched(const gtsr_meshlet* const* host_meshlets, const uint32_t* meshlet_counts,
-                          const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
-                          const uint32_t* targets, uint32_t n_targets, const gtsr_launch_cfg* cfgs,
+/* Pick the batched decoder's launch shape, LDS tile, launch mode and
+ * work-list granularity by measurement (the paper decodes one meshlet per
+ * workgroup and has no such knob).  format: GTSR_FORMAT_REUSE
+ * (decode_meshlets_batched) or GTSR_FORMAT_GTS (gtsr_decode_gts_batched).
+ * The caller passes n_works candidate work lists for the table, already on
+ * the device (dev_works[i] of work_counts[i] items, typically
+ * gtsr_plan_batch at different targets), and the candidates are every list
+ * times every shape in cfgs[n_cfgs] (NULL or 0 = the built-in shapes:
+ * static-split grids of 32 wavefronts per CU and 4, 8 and 16 times that,
+ * each with run_tris 1280 and 1024, the 1280 ones for GTS-Reuse only; and,
+ * when a workspace is given, persistent grids of 32 one-wavefront groups
+ * per CU claiming 1, 2 or 4 items at a time with the default tile).
+ * dev_workspace / workspace_bytes: as for decode_meshlets_batched, needed
+ * by claiming shapes (may be NULL when no shape claims).  Protocol: every
+ * candidate once untimed; a warm-up of back-to-back launches (about 60 ms
+ * of device time); then reps rounds (0 = 5, at most 1000), each enqueuing
+ * every candidate in turn, 4 launches each, with HIP events between
+ * candidates and no host wait inside a stage, so the device never idles
+ * while measuring; a candidate's figure is the median over rounds of its
+ * per-launch time.  The 4 fastest are measured again alone over 3 * reps
+ * rounds; among them the first in candidate order (list-major) whose median
+ * is within 1 % of the fastest is *best (target_tris holds its list index).
+ * points (may be NULL) receives up to capacity points, one per candidate in
+ * candidate order (the finalists' figures from the second stage), and
+ * *point_count (may be NULL) the number of candidates.  Synchronous:
+ * returns after the last timed launch.  Allocates no device memory.  Every
+ * launch decodes the whole table, so the table's outputs hold the decoded
+ * meshes on return.  Errors: EINVAL (null argument, bad format, bad cfg),
+ * EHIP. */
+int gtsr_autotune_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count, uint32_t format,
+                          const gtsr_work_item* const* dev_works, const uint32_t* work_counts, uint32_t n_works,
+                          void* dev_workspace, uint64_t workspace_bytes, const gtsr_launch_cfg* cfgs,
                           uint32_t n_cfgs, uint32_t reps, gtsr_tune_point* points, uint32_t capacity,
                           uint32_t* point_count, gtsr_tune_point* best, void* hip_stream);
 
@@ -476,17 +520,40 @@ typedef struct gtsr_attr_stream {
   const float* delta;
   uint32_t meshlet_count;
   uint32_t channels;          /* 1..64 */
+  uint64_t offset_count;      /* elements the offsets array holds (vert_off[M] * channels for a
+                                 well-formed stream); no offset at or past it is read */
 } gtsr_attr_stream;
 
 /* Dequantize on the GPU: dev_out float32[vert_off[M]][channels] receives
  * (lowest + offset) * delta + origin per meshlet-local vertex and channel,
  * computed as one float64 fused multiply-add rounded to float32, so copies of
  * a vertex in different meshlets get identical bits.  out_count: elements the
- * output holds; meshlets whose range passes it are skipped.  cfg (may be
+ * output holds; meshlets whose range passes it or dev->offset_count (or whose
+ * vert_off entries decrease) are skipped.  cfg (may be
  * NULL): waves_per_group 1..4, meshlets_per_wave.  Enqueued on hip_stream,
  * allocates nothing.  Errors: EINVAL, EHIP. */
 int gtsr_dequantize(const gtsr_attr_stream* dev, float* dev_out, uint64_t out_count, const gtsr_launch_cfg* cfg,
                     void* hip_stream);
+
+/* ------------------------------------------- bandwidth calibration */
+
+/* Achievable HBM bandwidth for the decoders' traffic mix (not in the paper:
+ * the yardstick the batched decode is measured against, beside the 8 TB/s
+ * peak).  The decode reads about 0.24 of its bytes (descriptors, flag chunks,
+ * reuse bytes; Sec. 4.2 / 4.3's streams) and writes 0.76 (Sec. 3's 3-byte
+ * triples) with 16-byte loads and non-temporal 16-byte stores, each
+ * wavefront walking contiguous blocks.  This kernel does that memory work
+ * alone: *steps_out = min(src_bytes / 4096, dst_bytes / 13312) steps, each
+ * reading 4 KiB of dev_src and writing 13 KiB of dev_dst (contiguous per
+ * wavefront, XCD-major, loads one step ahead of the stores that use them).
+ * Bytes moved per launch = 17408 * steps.  dev_dst receives values derived
+ * from dev_src (no meaning).  cfg (may be NULL): waves_per_group 1..16 (0 =
+ * 1), groups_per_cu 1..1024 (0 = 256); meshlets_per_wave and run_tris must
+ * be 0.  Both buffers 16-byte aligned, device memory.  Enqueued on
+ * hip_stream, allocates nothing.  Errors: EINVAL, ELIMIT (more than 2^32-1
+ * steps, or over 2 GiB of dst per wavefront), EHIP. */
+int gtsr_stream_calib(const uint8_t* dev_src, uint64_t src_bytes, uint8_t* dev_dst, uint64_t dst_bytes,
+                      const gtsr_launch_cfg* cfg, uint64_t* steps_out, void* hip_stream);
 
 /* Enqueue a captured graph on hip_stream.  Errors: EINVAL, EHIP. */
 int gtsr_graph_launch(void* graph_exec, void* hip_stream);

@@ -27,7 +27,10 @@ import numpy as np
 SEED_ROOT = (2404, 6359)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmeshgen.so")
+# MESHGEN_LIBRARY names another build of meshgen.c (the sanitized one, see
+# build_sanitized); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("MESHGEN_LIBRARY") or os.path.join(HERE, "libmeshgen.so")
+SANITIZED_PATH = os.path.join(os.path.dirname(HERE), "_build", "sanitize", "libmeshgen.so")
 _lib = None
 _lib_lock = threading.Lock()
 
@@ -39,6 +42,17 @@ def build() -> str:
                     os.path.join(HERE, "meshgen.c"), "-lm"], check=True)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
+
+
+def build_sanitized() -> str:
+    """``meshgen.c`` with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc), into ``_build/sanitize/libmeshgen.so``, for CPU test runs."""
+    os.makedirs(os.path.dirname(SANITIZED_PATH), exist_ok=True)
+    subprocess.run(["gcc", "-O1", "-g", "-std=c99", "-Wall", "-shared", "-fPIC", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-o", SANITIZED_PATH + ".tmp",
+                    os.path.join(HERE, "meshgen.c"), "-lm"], check=True)
+    os.replace(SANITIZED_PATH + ".tmp", SANITIZED_PATH)
+    return SANITIZED_PATH
 
 
 def _clib():

@@ -18,7 +18,10 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIBRARY names another build of oracle.c (the sanitized one, see
+# build_sanitized); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("ORACLE_LIBRARY") or os.path.join(HERE, "liboracle.so")
+SANITIZED_PATH = os.path.join(os.path.dirname(HERE), "_build", "sanitize", "liboracle.so")
 
 OK, EINVAL, ENOMEM, EDEGENERATE, ELIMIT, ECORRUPT = 0, -1, -2, -3, -4, -5
 
@@ -33,6 +36,17 @@ def build() -> str:
                     "-o", tmp, src, "-lm"], check=True)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
+
+
+def build_sanitized() -> str:
+    """``oracle.c`` with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc), into ``_build/sanitize/liboracle.so``, for CPU test runs."""
+    os.makedirs(os.path.dirname(SANITIZED_PATH), exist_ok=True)
+    subprocess.run(["gcc", "-O1", "-g", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
+                    "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                    "-o", SANITIZED_PATH + ".tmp", os.path.join(HERE, "oracle.c"), "-lm"], check=True)
+    os.replace(SANITIZED_PATH + ".tmp", SANITIZED_PATH)
+    return SANITIZED_PATH
 
 
 def lib():

@@ -15,7 +15,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libgtsr.so")
+# GTSR_LIBRARY names another build of the same library (the host-sanitized
+# one for CPU test runs); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("GTSR_LIBRARY") or os.path.join(PKG, "libgtsr.so")
 
 OK, EINVAL, ENOMEM, EDEGENERATE, ELIMIT, ECORRUPT, EHIP = 0, -1, -2, -3, -4, -5, -6
 FORMAT_REUSE, FORMAT_GTS = 0, 1
@@ -29,7 +31,7 @@ EXPORTED = (
     "gtsr_server_get_stats", "gtsr_server_replay", "gtsr_server_destroy",
     "gtsr_gts_from_reuse", "gtsr_decode_gts", "gtsr_decode_gts_batched", "gtsr_decode_compact",
     "gtsr_quantize_attributes", "gtsr_dequantize", "gtsr_min_strips", "gtsr_meshlet_cones",
-    "gtsr_decode_culled",
+    "gtsr_decode_culled", "gtsr_stream_calib",
 )
 
 
@@ -72,23 +74,28 @@ class StreamDesc(C.Structure):
 
 class LaunchCfg(C.Structure):
     _fields_ = [("waves_per_group", C.c_uint32), ("meshlets_per_wave", C.c_uint32),
-                ("groups_per_cu", C.c_uint32), ("run_tris", C.c_uint32)]
+                ("groups_per_cu", C.c_uint32), ("run_tris", C.c_uint32), ("items_per_claim", C.c_uint32)]
+
+
+BATCHED_WORKSPACE_BYTES = 1024   # GTSR_BATCHED_WORKSPACE_BYTES
 
 
 class TunePoint(C.Structure):
     _fields_ = [("target_tris", C.c_uint32), ("work_items", C.c_uint32), ("cfg", LaunchCfg),
-                ("median_ms", C.c_float), ("min_ms", C.c_float)]
+                ("median_ms", C.c_float), ("min_ms", C.c_float), ("stage", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
     def as_dict(self) -> dict:
         return {"target_tris": self.target_tris, "work_items": self.work_items,
                 "waves_per_group": self.cfg.waves_per_group, "groups_per_cu": self.cfg.groups_per_cu,
-                "run_tris": self.cfg.run_tris, "median_ms": self.median_ms, "min_ms": self.min_ms}
+                "run_tris": self.cfg.run_tris, "items_per_claim": self.cfg.items_per_claim,
+                "median_ms": self.median_ms, "min_ms": self.min_ms, "stage": self.stage}
 
 
 class AttrStream(C.Structure):
     _fields_ = [("lowest", C.c_void_p), ("offsets", C.c_void_p), ("vert_off", C.c_void_p),
                 ("origin", C.c_void_p), ("delta", C.c_void_p), ("meshlet_count", C.c_uint32),
-                ("channels", C.c_uint32)]
+                ("channels", C.c_uint32), ("offset_count", C.c_uint64)]
 
 
 class ServerParams(C.Structure):
@@ -137,14 +144,15 @@ def lib():
         "decode_meshlets": (C.c_int, [C.POINTER(StreamDesc), vp, u64, vp]),
         "gtsr_decode_meshlets_cfg": (C.c_int, [C.POINTER(StreamDesc), vp, u64, C.POINTER(LaunchCfg), vp]),
         "gtsr_decode_meshlets_many": (C.c_int, [vp, vp, vp, u32, C.POINTER(LaunchCfg), vp]),
-        "decode_meshlets_batched": (C.c_int, [vp, u32, vp, u32, C.POINTER(LaunchCfg), vp]),
-        "gtsr_batched_graph_create": (C.c_int, [vp, u32, vp, u32, C.POINTER(LaunchCfg), C.POINTER(vp)]),
+        "decode_meshlets_batched": (C.c_int, [vp, u32, vp, u32, vp, u64, C.POINTER(LaunchCfg), vp]),
+        "gtsr_batched_graph_create": (C.c_int, [vp, u32, vp, u32, vp, u64, u32, C.POINTER(LaunchCfg),
+                                                C.POINTER(vp)]),
         "gtsr_graph_launch": (C.c_int, [vp, vp]),
         "gtsr_graph_destroy": (None, [vp]),
         "gtsr_device_cu_count": (u32, []),
         "gtsr_last_error": (C.c_char_p, []),
-        "gtsr_autotune_batched": (C.c_int, [vp, vp, vp, u32, vp, u32, vp, u32, u32, vp, u32, C.POINTER(u32),
-                                            C.POINTER(TunePoint), vp]),
+        "gtsr_autotune_batched": (C.c_int, [vp, u32, u32, vp, vp, u32, vp, u64, vp, u32, u32, vp, u32,
+                                            C.POINTER(u32), C.POINTER(TunePoint), vp]),
         "gtsr_server_create": (C.c_int, [vp, vp, u32, C.POINTER(ServerParams), C.POINTER(vp)]),
         "gtsr_server_submit": (C.c_int, [vp, u32, u64]),
         "gtsr_server_poll": (C.c_int, [vp, vp, u32, C.POINTER(u32), u32]),
@@ -154,7 +162,7 @@ def lib():
         "gtsr_server_destroy": (None, [vp]),
         "gtsr_gts_from_reuse": (C.c_int, [C.POINTER(StreamDesc), vp, vp, u64, vp, u64]),
         "gtsr_decode_gts": (C.c_int, [C.POINTER(StreamDesc), vp, u64, C.POINTER(LaunchCfg), vp]),
-        "gtsr_decode_gts_batched": (C.c_int, [vp, u32, vp, u32, C.POINTER(LaunchCfg), vp]),
+        "gtsr_decode_gts_batched": (C.c_int, [vp, u32, vp, u32, vp, u64, C.POINTER(LaunchCfg), vp]),
         "gtsr_decode_compact": (C.c_int, [C.POINTER(StreamDesc), u32, vp, vp, u64, C.POINTER(LaunchCfg), vp]),
         "gtsr_quantize_attributes": (C.c_int, [vp, u32, u32, vp, vp, u32, u32, vp, vp, vp, vp]),
         "gtsr_dequantize": (C.c_int, [C.POINTER(AttrStream), vp, u64, C.POINTER(LaunchCfg), vp]),
@@ -162,6 +170,7 @@ def lib():
         "gtsr_meshlet_cones": (C.c_int, [vp, u64, vp, u32, vp, vp, u32, vp]),
         "gtsr_decode_culled": (C.c_int, [C.POINTER(StreamDesc), vp, C.c_float, C.c_float, C.c_float, vp, u64,
                                          C.POINTER(LaunchCfg), vp]),
+        "gtsr_stream_calib": (C.c_int, [vp, u64, vp, u64, C.POINTER(LaunchCfg), C.POINTER(u64), vp]),
     }
     for name, (rt, args) in sig.items():
         f = getattr(L, name)
@@ -183,7 +192,7 @@ def _cfg(cfg) -> C.POINTER(LaunchCfg):
     if isinstance(cfg, LaunchCfg):
         return C.byref(cfg)
     c = LaunchCfg(int(cfg.get("waves_per_group", 0)), int(cfg.get("meshlets_per_wave", 0)),
-                  int(cfg.get("groups_per_cu", 0)), int(cfg.get("run_tris", 0)))
+                  int(cfg.get("groups_per_cu", 0)), int(cfg.get("run_tris", 0)), int(cfg.get("items_per_claim", 0)))
     return C.byref(c)
 
 
@@ -466,12 +475,14 @@ class Batch:
         self.work_items = int(items.shape[0])
         self.work = torch.from_numpy(items.view(np.uint8).reshape(-1).copy()).to(device)
         self.mesh_count = n
+        self.workspace = torch.zeros(BATCHED_WORKSPACE_BYTES, dtype=torch.uint8, device=device)
         self._graphs = []
 
     def launch(self, stream=None, cfg=None):
         L = lib()
         _check(L.decode_meshlets_batched(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
-                                         self.work_items, _cfg(cfg), _stream_handle(stream)))
+                                         self.work_items, self.workspace.data_ptr(), self.workspace.numel(),
+                                         _cfg(cfg), _stream_handle(stream)))
         return self.outs
 
     def graph(self, cfg=None):
@@ -479,29 +490,48 @@ class Batch:
         L = lib()
         h = C.c_void_p()
         _check(L.gtsr_batched_graph_create(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
-                                           self.work_items, _cfg(cfg), C.byref(h)))
-        g = Graph(h)
+                                           self.work_items, self.workspace.data_ptr(), self.workspace.numel(),
+                                           FORMAT_REUSE, _cfg(cfg), C.byref(h)))
+        g = Graph(h, keep=(self.table, self.work, self.workspace))
         self._graphs.append(g)
         return g
 
 
 class Graph:
-    def __init__(self, handle):
+    """A captured batched decode.  It holds the tensors whose addresses the
+    graph baked in (mesh table, work list), so they outlive it; a ``Pool``
+    closes its graphs when it is re-planned."""
+
+    def __init__(self, handle, keep=()):
         self.handle = handle
+        self._keep = keep
 
     def __call__(self, stream=None):
+        if not self.handle:
+            raise RuntimeError("this graph was closed (its pool was re-planned or closed): capture a new one")
         _check(lib().gtsr_graph_launch(self.handle, _stream_handle(stream)))
 
     def close(self):
         if self.handle:
             lib().gtsr_graph_destroy(self.handle)
             self.handle = None
+        self._keep = ()
 
     def __del__(self):
         try:
             self.close()
         except Exception:
             pass
+
+
+def stream_calib(src, dst, stream=None, cfg=None) -> int:
+    """One launch of the bandwidth calibration kernel (``gtsr_stream_calib``):
+    reads 4 KiB of ``src`` and writes 13 KiB of ``dst`` (device uint8
+    tensors) per step; returns the step count (17408 bytes moved per step)."""
+    steps = C.c_uint64()
+    _check(lib().gtsr_stream_calib(src.data_ptr(), src.numel(), dst.data_ptr(), dst.numel(), _cfg(cfg),
+                                   C.byref(steps), _stream_handle(stream)))
+    return int(steps.value)
 
 
 def device_cu_count() -> int:
@@ -575,6 +605,7 @@ class Pool:
         self.out_bytes = (C.c_uint64 * max(n, 1))(*[int(x) for x in 3 * self.strip_tris])
         self.work = None
         self.work_items = 0
+        self.workspace = torch.zeros(BATCHED_WORKSPACE_BYTES, dtype=torch.uint8, device=device)
         self._graphs = []
 
     def output(self, i: int):
@@ -584,57 +615,75 @@ class Pool:
 
     def plan(self, target_tris: int = 768):
         torch = _torch()
+        # graphs captured before hold the old work list's address and length
+        for g in self._graphs:
+            g.close()
+        self._graphs = []
         items = plan_batch(self.host_meshlets, target_tris)
         self.work_items = int(items.shape[0])
         self.work = torch.from_numpy(items.view(np.uint8).reshape(-1).copy()).to(self.table.device) \
             if items.size else torch.zeros(16, dtype=torch.uint8, device=self.table.device)
         return self
 
+    TUNE_TARGETS = (384, 768, 1536, 3072)
+
     def autotune(self, targets=None, cfgs=None, reps: int = 5, stream=None):
-        """Measure the batched decoder over launch shapes (``gtsr_autotune_batched``),
-        re-plan with the fastest target and return ``(best_cfg, best, points)``:
-        ``best_cfg`` is a dict for ``decode_batched`` / ``batched_graph``,
-        ``best`` and ``points`` are ``TunePoint.as_dict()`` records."""
-        if self.format != FORMAT_REUSE:
-            raise ValueError("the autotuner measures GTS-Reuse pools")
+        """Measure the batched decoder over work-list targets x launch shapes
+        (``gtsr_autotune_batched``) and keep the fastest: the pool's work list
+        becomes the winning one (planned and uploaded before measuring, so no
+        host work separates tuning from use).  Returns ``(best_cfg, best,
+        points)``: ``best_cfg`` is a dict for ``decode_batched`` /
+        ``batched_graph``; ``best`` and ``points`` are ``TunePoint.as_dict()``
+        records whose ``target_tris`` is the target (not the list index)."""
+        torch = _torch()
         L = lib()
-        n = self.mesh_count
-        arrs = [np.ascontiguousarray(a, MESHLET_DTYPE) for a in self.host_meshlets]
-        ptrs = (C.c_void_p * max(n, 1))(*[a.ctypes.data if a.size else None for a in arrs])
-        tg = np.array(targets or [], np.uint32)
+        tg = [int(t) for t in (targets or self.TUNE_TARGETS)]
+        lists = [plan_batch(self.host_meshlets, t) for t in tg]
+        dev = [torch.from_numpy(x.view(np.uint8).reshape(-1).copy()).to(self.table.device) if x.size
+               else torch.zeros(16, dtype=torch.uint8, device=self.table.device) for x in lists]
+        ptrs = (C.c_void_p * len(tg))(*[d.data_ptr() for d in dev])
+        counts = np.array([x.shape[0] for x in lists], np.uint32)
         cf = (LaunchCfg * max(len(cfgs or []), 1))()
         for i, c in enumerate(cfgs or []):
             cf[i] = LaunchCfg(int(c.get("waves_per_group", 0)), 0, int(c.get("groups_per_cu", 0)),
-                              int(c.get("run_tris", 0)))
-        cap = max(1, len(tg) or 4) * max(1, len(cfgs or []) or 18)
+                              int(c.get("run_tris", 0)), int(c.get("items_per_claim", 0)))
+        cap = len(tg) * max(1, len(cfgs or []) or 21)   # at most 21 built-in shapes
         pts = (TunePoint * cap)()
         cnt = C.c_uint32()
         best = TunePoint()
-        _check(L.gtsr_autotune_batched(ptrs, self.meshlet_counts.ctypes.data, self.table.data_ptr(), n,
-                                       tg.ctypes.data if tg.size else None, int(tg.size),
+        _check(L.gtsr_autotune_batched(self.table.data_ptr(), self.mesh_count, self.format, ptrs,
+                                       counts.ctypes.data, len(tg), self.workspace.data_ptr(), self.workspace.numel(),
                                        cf if cfgs else None, len(cfgs or []), reps, pts, cap, C.byref(cnt),
                                        C.byref(best), _stream_handle(stream)))
-        self.plan(int(best.target_tris))
+        k = int(best.target_tris)
+        for g in self._graphs:
+            g.close()
+        self._graphs = []
+        self.work, self.work_items = dev[k], int(counts[k])
         cfg = {"waves_per_group": int(best.cfg.waves_per_group), "groups_per_cu": int(best.cfg.groups_per_cu),
-               "run_tris": int(best.cfg.run_tris)}
-        return cfg, best.as_dict(), [pts[i].as_dict() for i in range(min(cnt.value, cap))]
+               "run_tris": int(best.cfg.run_tris), "items_per_claim": int(best.cfg.items_per_claim)}
+
+        def rec(p):
+            d = p.as_dict()
+            d["target_tris"] = tg[int(p.target_tris)]
+            return d
+        return cfg, rec(best), [rec(pts[i]) for i in range(min(cnt.value, cap))]
 
     def decode_batched(self, stream=None, cfg=None):
         if self.work is None:
             self.plan()
         f = lib().gtsr_decode_gts_batched if self.format == FORMAT_GTS else lib().decode_meshlets_batched
-        _check(f(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
-                                             self.work_items, _cfg(cfg), _stream_handle(stream)))
+        _check(f(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(), self.work_items,
+                 self.workspace.data_ptr(), self.workspace.numel(), _cfg(cfg), _stream_handle(stream)))
 
     def batched_graph(self, cfg=None):
-        if self.format != FORMAT_REUSE:
-            raise ValueError("graph capture covers GTS-Reuse pools")
         if self.work is None:
             self.plan()
         h = C.c_void_p()
         _check(lib().gtsr_batched_graph_create(self.table.data_ptr(), self.mesh_count, self.work.data_ptr(),
-                                               self.work_items, _cfg(cfg), C.byref(h)))
-        g = Graph(h)
+                                               self.work_items, self.workspace.data_ptr(), self.workspace.numel(),
+                                               self.format, _cfg(cfg), C.byref(h)))
+        g = Graph(h, keep=(self.table, self.work, self.workspace))
         self._graphs.append(g)
         return g
 
@@ -657,7 +706,7 @@ class Server:
         self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=pool.table.device)
         base = self.arena.data_ptr()
         self._arena_base = (base + 255) // 256 * 256
-        c = LaunchCfg(0, 0, 0, 0)
+        c = LaunchCfg(0, 0, 0, 0, 0)
         if cfg:
             c = LaunchCfg(int(cfg.get("waves_per_group", 0)), 0, int(cfg.get("groups_per_cu", 0)),
                           int(cfg.get("run_tris", 0)))
@@ -760,20 +809,22 @@ class DeviceAttrs:
     delta: object
     meshlet_count: int
     channels: int
+    offset_count: int
 
     def desc(self) -> AttrStream:
         return AttrStream(self.lowest.data_ptr(), self.offsets.data_ptr(), self.vert_off.data_ptr(),
-                          self.origin.data_ptr(), self.delta.data_ptr(), self.meshlet_count, self.channels)
+                          self.origin.data_ptr(), self.delta.data_ptr(), self.meshlet_count, self.channels,
+                          self.offset_count)
 
     @property
     def elements(self) -> int:
-        return self.offsets.numel() // 2
+        return self.offset_count
 
 
 def attrs_to_device(q: QuantizedAttrs, device="cuda") -> DeviceAttrs:
     up = lambda a: upload_padded(np.ascontiguousarray(a), device)
     return DeviceAttrs(up(q.lowest), up(q.offsets), up(q.vert_off), up(q.origin), up(q.delta),
-                       int(q.lowest.shape[0]), int(q.origin.shape[0]))
+                       int(q.lowest.shape[0]), int(q.origin.shape[0]), int(q.offsets.size))
 
 
 def dequantize(da: DeviceAttrs, out=None, stream=None, cfg=None):

@@ -22,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")
 
 HOST_SOURCES = ["encode.cpp", "capi.cpp", "tune.cpp", "serve.cpp", "quant.cpp", "cones.cpp"]
-HIP_SOURCES = ["decode.hip", "attrs.hip"]
+HIP_SOURCES = ["decode.hip", "attrs.hip", "calib.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]
 # Host files that call the HIP runtime API (autotuner, server) compile with g++.
@@ -62,5 +62,39 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SANITIZE_DIR = os.path.join(BUILD, "sanitize")
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """A host-sanitized copy of the library for CPU test runs:
+    ``_build/sanitize/libgtsr.so``.  The host C++ (encoder, validator,
+    planner, quantizer, cones, tuner, server) is compiled by g++ with
+    AddressSanitizer and UndefinedBehaviorSanitizer; the HIP translation
+    units keep their normal build (no sanitizer reaches device code).  Load
+    it by setting GTSR_LIBRARY to its path, with the sanitizer runtime
+    preloaded into the Python process."""
+    os.makedirs(SANITIZE_DIR, exist_ok=True)
+    jobs, objs = [], []
+    for src in HOST_SOURCES:
+        obj = os.path.join(SANITIZE_DIR, src + ".o")
+        jobs.append([CXX, "-O1", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, *HIP_HOST, *SANITIZE,
+                     "-pthread", "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    for src in HIP_SOURCES:
+        obj = os.path.join(SANITIZE_DIR, src + ".o")
+        jobs.append([HIPCC, *COMMON, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    with ThreadPoolExecutor(len(jobs)) as ex:
+        for r in ex.map(_run, jobs):
+            if verbose and (r.stdout or r.stderr):
+                sys.stderr.write(r.stdout + r.stderr)
+    out = os.path.join(SANITIZE_DIR, "libgtsr.so")
+    _run([CXX, "-shared", "-fPIC", "-pthread", *SANITIZE, *objs, "-L/opt/rocm/lib", "-lamdhip64",
+          "-Wl,-rpath,/opt/rocm/lib", "-o", out + ".tmp"])
+    os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build_sanitized(verbose=True) if "--sanitize" in sys.argv else build(verbose=True))

@@ -27,7 +27,8 @@ __global__ __launch_bounds__(256) void k_dequantize(const int32_t* __restrict__ 
                                                     const uint64_t* __restrict__ vert_off,
                                                     const float* __restrict__ origin,
                                                     const float* __restrict__ delta, float* __restrict__ out,
-                                                    uint32_t meshlet_count, uint32_t channels, uint64_t out_count) {
+                                                    uint32_t meshlet_count, uint32_t channels, uint64_t out_count,
+                                                    uint64_t offset_count) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const uint32_t waves = blockDim.x / kWave;
@@ -37,9 +38,13 @@ __global__ __launch_bounds__(256) void k_dequantize(const int32_t* __restrict__ 
   const uint64_t x0 = uint64_t(meshlet_count) * xcd / kXcds, x1 = uint64_t(meshlet_count) * (xcd + 1) / kXcds;
   const uint32_t m0 = uint32_t(x0 + (x1 - x0) * qi / wx), m1 = uint32_t(x0 + (x1 - x0) * (qi + 1) / wx);
   const uint32_t step = kWave % channels;
+  // vertex offsets past this bound address elements neither array holds (and
+  // bounding them first keeps the products below from overflowing)
+  const uint64_t v_limit = (out_count < offset_count ? out_count : offset_count) / channels;
   for (uint32_t m = m0; m < m1; ++m) {
-    const uint64_t e0 = vert_off[m] * channels, e1 = vert_off[m + 1] * channels;
-    if (e1 < e0 || e1 > out_count) continue;   // corrupt offsets: the meshlet is skipped
+    const uint64_t v0 = vert_off[m], v1 = vert_off[m + 1];
+    if (v1 < v0 || v1 > v_limit) continue;   // corrupt offsets: the meshlet is skipped
+    const uint64_t e0 = v0 * channels, e1 = v1 * channels;
     const int32_t* Lm = lowest + uint64_t(m) * channels;
     uint32_t ch = lane % channels;
     for (uint64_t e = e0 + lane; e < e1; e += kWave) {
@@ -77,7 +82,7 @@ extern "C" int gtsr_dequantize(const gtsr_attr_stream* dev, float* dev_out, uint
   groups = (groups + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(k_dequantize, dim3(uint32_t(groups)), dim3(kWave * waves), 0,
                      static_cast<hipStream_t>(hip_stream), dev->lowest, dev->offsets, dev->vert_off, dev->origin,
-                     dev->delta, dev_out, dev->meshlet_count, dev->channels, out_count);
+                     dev->delta, dev_out, dev->meshlet_count, dev->channels, out_count, dev->offset_count);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(GTSR_EHIP, std::string(who) + ": " + hipGetErrorString(e));
   return ok();

@@ -42,7 +42,6 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
-#include <vector>
 
 #include "common.h"
 
@@ -511,7 +510,11 @@ __device__ __forceinline__ uint4 load_bits(const Stream& s, const Plan& p, uint3
         u32x2, __builtin_amdgcn_raw_buffer_load_b64(buffer(s.bits + 8ull * p.c0, 8 * p.nch), int(8 * lane), 0, 0));
     return make_uint4(v.x, v.y, 0, 0);
   }
-  return load16(buffer(s.bits + 16ull * p.c0, 16 * p.nch), 16 * lane);
+  // one dword per 16-byte chunk brings its cache line in and keeps three
+  // VGPRs per pipeline stage free
+  const uint32_t w = uint32_t(__builtin_amdgcn_raw_buffer_load_b32(buffer(s.bits + 16ull * p.c0, 16 * p.nch),
+                                                                   int(16 * lane), 0, 0));
+  return make_uint4(w, 0, 0, 0);
 }
 
 // The reuse allocation extends to a multiple of 16 bytes, so whole blocks can
@@ -667,7 +670,7 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
     if constexpr (kPlain)
       asm volatile("" ::"v"(bv.x), "v"(bv.y));
     else
-      asm volatile("" ::"v"(bv.x), "v"(bv.y), "v"(bv.z), "v"(bv.w));
+      asm volatile("" ::"v"(bv.x));
     decode_run<kPlain, kCompact, kTile>(tile, lp, p, layout, tri_counts, s.bits + (kPlain ? 8ull : 16ull) * p.c0, lane);
     store_run<kPlain, kTile>(s.out + 3ull * p.o0, p.shift, p.tris, tile, lane);
     wave_lds_sync();
@@ -734,20 +737,13 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
   decode_range<kPlain, kCompact, kCull, kTile>(s, b0, b1, tile, lp, lane);
 }
 
-// Persistent batched decoder: every wavefront takes one contiguous block of
-// the work list (items are balanced by strip triangles) and decodes it as
-// meshlet ranges, merging consecutive items that continue the same mesh.
-// kPlain: every entry holds a plain GTS stream; kTile: the LDS tile (Shape).
+// Decodes work items [b0, b1) of the batched work list with the calling
+// wavefront: 64 items at a time, one per lane, merging consecutive items that
+// continue the same mesh into one meshlet range.
 template <bool kPlain, uint32_t kTile>
-__global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
-    const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
-    const gtsr_work_item* __restrict__ work, uint32_t work_items) {
-  const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t wave = uniform(threadIdx.x / kWave);
-  LanePtrs lp;
-  RunTile<kPlain, kTile>& tile = wave_tile<kPlain, kTile>(wave, lane, lp);
-  uint32_t b0, b1;
-  wave_block(work_items, wave, blockDim.x / kWave, b0, b1);
+__device__ __forceinline__ void decode_items(const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
+                                             const gtsr_work_item* __restrict__ work, uint32_t b0, uint32_t b1,
+                                             RunTile<kPlain, kTile>& tile, const LanePtrs& lp, uint32_t lane) {
   for (uint64_t base = b0; base < b1; base += kWave) {
     const uint32_t cnt = uint32_t(min(b1 - base, uint64_t(kWave)));
     uint4 wi = make_uint4(0xFFFFFFFFu, 0, 0, 0);
@@ -780,9 +776,75 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched(
   }
 }
 
+// Batched decoder, static split: every wavefront of an over-subscribed grid
+// takes one contiguous block of the work list (items are balanced by strip
+// triangles) and exits; the dispatcher refills freed slots with the next
+// groups, so the blocks of one XCD are decoded roughly in list order.
+// kPlain: every entry holds a plain GTS stream; kTile: the LDS tile (Shape).
+// Eight wavefronts per SIMD (64 VGPRs; the compiler spills one 8-byte value
+// outside the run loop) measured 0.5% faster than seven without the spill.
+template <bool kPlain, uint32_t kTile>
+__global__ __launch_bounds__(kWave * kMaxWavesPerGroup) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_decode_batched(
+    const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
+    const gtsr_work_item* __restrict__ work, uint32_t work_items) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t wave = uniform(threadIdx.x / kWave);
+  LanePtrs lp;
+  RunTile<kPlain, kTile>& tile = wave_tile<kPlain, kTile>(wave, lane, lp);
+  uint32_t b0, b1;
+  wave_block(work_items, wave, blockDim.x / kWave, b0, b1);
+  decode_items<kPlain, kTile>(table, mesh_count, work, b0, b1, tile, lp, lane);
+}
+
+// Batched decoder, persistent with claimed work: a grid of about the
+// resident wavefront count, whose waves claim per_claim consecutive items at
+// a time from a counter of their XCD's share of the list (workgroups go
+// round-robin over the 8 XCDs, so each XCD's waves claim from their own
+// counter, in their own cache lines) until the share runs out.  Each claim's
+// atomic is issued one claim ahead, so its return is in by the time the
+// items before it are decoded.  The counters must be zero at the launch
+// (k_claim_reset in front, in the same stream); a claim past the share ends
+// the wave, so every wave exits.
+constexpr uint32_t kClaimStride = 32;                    // 32-bit words between counters: one per 128-byte line
+constexpr uint32_t kClaimWords = kXcds * kClaimStride;   // 1 KiB of workspace
+
+__device__ __forceinline__ uint32_t claim_issue(uint32_t* ctr, uint32_t per_claim, uint32_t lane) {
+  uint32_t v = 0;
+  if (lane == 0) v = __hip_atomic_fetch_add(ctr, per_claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return v;   // lane 0's value; read with uniform() only when it is needed
+}
+
+template <bool kPlain, uint32_t kTile>
+__global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched_claim(
+    const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
+    const gtsr_work_item* __restrict__ work, uint32_t work_items, uint32_t* __restrict__ counters,
+    uint32_t per_claim) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t wave = uniform(threadIdx.x / kWave);
+  LanePtrs lp;
+  RunTile<kPlain, kTile>& tile = wave_tile<kPlain, kTile>(wave, lane, lp);
+  const uint32_t xcd = blockIdx.x % kXcds;
+  const uint32_t x0 = uint32_t(uint64_t(work_items) * xcd / kXcds);
+  const uint32_t len = uint32_t(uint64_t(work_items) * (xcd + 1) / kXcds) - x0;
+  uint32_t* ctr = counters + xcd * kClaimStride;
+  uint32_t c = uniform(claim_issue(ctr, per_claim, lane));
+  while (c < len) {
+    const uint32_t next = claim_issue(ctr, per_claim, lane);
+    decode_items<kPlain, kTile>(table, mesh_count, work, x0 + c, x0 + min(c + per_claim, len), tile, lp, lane);
+    c = uniform(next);
+  }
+}
+
+// Zeroes the claim counters in front of a claiming launch (a kernel, so that
+// a captured graph holds no memset node).
+__global__ void k_claim_reset(uint32_t* __restrict__ counters) {
+  if (threadIdx.x < kClaimWords) counters[threadIdx.x] = 0;
+}
+
 struct Defaults {
   uint32_t waves = 4, mpw = 8, gpc = 8;
   uint32_t tile = 0;   // Shape tile index; GTS-Reuse: 0 = 1280-triangle runs, 1 = 1024
+  uint32_t claim = 0;  // batched: work items per claim (0 = static split)
 };
 
 // run_tris (batched decoders only): 0 = the default tile, else the run
@@ -809,17 +871,23 @@ int resolve_cfg(const gtsr_launch_cfg* cfg, Defaults& d, const char* who, bool b
       return fail(GTSR_EINVAL, std::string(who) + ": groups_per_cu > 1024");
     d.gpc = cfg->groups_per_cu;
   }
+  if (cfg->items_per_claim) {
+    if (!batched) return fail(GTSR_EINVAL, std::string(who) + ": cfg.items_per_claim must be 0 (batched decoders only)");
+    if (cfg->items_per_claim > 1024) return fail(GTSR_EINVAL, std::string(who) + ": items_per_claim > 1024");
+    d.claim = cfg->items_per_claim;
+  }
   return GTSR_OK;
 }
 
+// Per-device caches, fixed-size so that no call after the first allocates.
+constexpr int kMaxDevices = 64;
 std::mutex g_cu_mutex;
-std::vector<uint32_t> g_cu_count;   // per device, 0 = not queried yet
+uint32_t g_cu_count[kMaxDevices];   // 0 = not queried yet
 
 uint32_t cu_count() {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
   std::lock_guard<std::mutex> lk(g_cu_mutex);
-  if (g_cu_count.size() <= size_t(dev)) g_cu_count.resize(dev + 1, 0);
   if (!g_cu_count[dev]) {
     int n = 0;
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 0;
@@ -837,11 +905,12 @@ int check_launch(const char* who) {
 inline uint32_t round_up8(uint64_t g) { return uint32_t((g + kXcds - 1) / kXcds * kXcds); }
 
 int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gtsr_work_item* work,
-                    uint32_t work_items, const gtsr_launch_cfg* cfg, hipStream_t stream, const char* who,
-                    bool plain = false) {
+                    uint32_t work_items, void* workspace, uint64_t workspace_bytes, const gtsr_launch_cfg* cfg,
+                    hipStream_t stream, const char* who, bool plain = false) {
   if ((mesh_count && !table) || (work_items && !work)) return fail(GTSR_EINVAL, std::string(who) + ": null pointer");
   if ((reinterpret_cast<uintptr_t>(table) & 15) || (reinterpret_cast<uintptr_t>(work) & 15))
     return fail(GTSR_EINVAL, std::string(who) + ": tables must be 16-byte aligned");
+  if (work_items > 0x80000000u) return fail(GTSR_EINVAL, std::string(who) + ": more than 2^31 work items");
   Defaults d;
   // measured best on the batched 2000-mesh workload: one-wave groups, 256 per
   // CU (about 9 times the resident count, so freed slots are refilled until
@@ -849,21 +918,43 @@ int enqueue_batched(const gtsr_mesh_entry* table, uint32_t mesh_count, const gts
   d.waves = 1;
   d.gpc = 256;
   if (int rc = resolve_cfg(cfg, d, who, true, plain)) return rc;
+  if (d.claim) {
+    if (!workspace || workspace_bytes < GTSR_BATCHED_WORKSPACE_BYTES)
+      return fail(GTSR_EINVAL, std::string(who) + ": claiming needs a workspace of GTSR_BATCHED_WORKSPACE_BYTES");
+    if (reinterpret_cast<uintptr_t>(workspace) & 3)
+      return fail(GTSR_EINVAL, std::string(who) + ": workspace must be 4-byte aligned");
+    if (!cfg->groups_per_cu) d.gpc = 32 / d.waves ? 32 / d.waves : 1;   // about the resident count
+  }
   const uint32_t cus = cu_count();
   if (!cus) return fail(GTSR_EHIP, std::string(who) + ": cannot query the device");
   if (work_items == 0) return ok();
-  // the configured grid, or fewer groups when the list has fewer items than that grid has wavefronts
-  const uint64_t want = (uint64_t(work_items) + d.waves - 1) / d.waves;
+  // the configured grid, or fewer groups when the list has fewer items (or
+  // claims) than that grid has wavefronts
+  const uint64_t units = d.claim ? (uint64_t(work_items) + d.claim - 1) / d.claim : work_items;
+  const uint64_t want = (units + d.waves - 1) / d.waves;
   const uint32_t groups = round_up8(std::min<uint64_t>(uint64_t(cus) * d.gpc, want));
+  const dim3 grid(groups), block(kWave * d.waves);
+  const uint32_t lds = d.waves * (plain ? kTileBytes<true, 0> : d.tile == 1 ? kTileBytes<false, 1> : kTileBytes<false, 0>);
+  if (d.claim) {
+    uint32_t* ctr = static_cast<uint32_t*>(workspace);
+    hipLaunchKernelGGL(k_claim_reset, dim3(1), dim3(kClaimWords), 0, stream, ctr);
+    if (plain)
+      hipLaunchKernelGGL((k_decode_batched_claim<true, 0>), grid, block, lds, stream, table, mesh_count, work,
+                         work_items, ctr, d.claim);
+    else if (d.tile == 1)
+      hipLaunchKernelGGL((k_decode_batched_claim<false, 1>), grid, block, lds, stream, table, mesh_count, work,
+                         work_items, ctr, d.claim);
+    else
+      hipLaunchKernelGGL((k_decode_batched_claim<false, 0>), grid, block, lds, stream, table, mesh_count, work,
+                         work_items, ctr, d.claim);
+    return check_launch(who);
+  }
   if (plain)
-    hipLaunchKernelGGL((k_decode_batched<true, 0>), dim3(groups), dim3(kWave * d.waves), d.waves * (kTileBytes<true, 0>),
-                       stream, table, mesh_count, work, work_items);
+    hipLaunchKernelGGL((k_decode_batched<true, 0>), grid, block, lds, stream, table, mesh_count, work, work_items);
   else if (d.tile == 1)
-    hipLaunchKernelGGL((k_decode_batched<false, 1>), dim3(groups), dim3(kWave * d.waves), d.waves * (kTileBytes<false, 1>),
-                       stream, table, mesh_count, work, work_items);
+    hipLaunchKernelGGL((k_decode_batched<false, 1>), grid, block, lds, stream, table, mesh_count, work, work_items);
   else
-    hipLaunchKernelGGL((k_decode_batched<false, 0>), dim3(groups), dim3(kWave * d.waves), d.waves * (kTileBytes<false, 0>),
-                       stream, table, mesh_count, work, work_items);
+    hipLaunchKernelGGL((k_decode_batched<false, 0>), grid, block, lds, stream, table, mesh_count, work, work_items);
   return check_launch(who);
 }
 
@@ -997,25 +1088,28 @@ extern "C" int gtsr_decode_culled(const gtsr_stream* dev, const float* dev_cones
 }
 
 extern "C" int gtsr_decode_gts_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
-                                       const gtsr_work_item* dev_work, uint32_t work_items,
-                                       const gtsr_launch_cfg* cfg, void* hip_stream) {
-  return enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, cfg,
+                                       const gtsr_work_item* dev_work, uint32_t work_items, void* dev_workspace,
+                                       uint64_t workspace_bytes, const gtsr_launch_cfg* cfg, void* hip_stream) {
+  return enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, dev_workspace, workspace_bytes, cfg,
                          static_cast<hipStream_t>(hip_stream), "gtsr_decode_gts_batched", true);
 }
 
 extern "C" int decode_meshlets_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
-                                       const gtsr_work_item* dev_work, uint32_t work_items,
-                                       const gtsr_launch_cfg* cfg, void* hip_stream) {
-  return enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, cfg,
+                                       const gtsr_work_item* dev_work, uint32_t work_items, void* dev_workspace,
+                                       uint64_t workspace_bytes, const gtsr_launch_cfg* cfg, void* hip_stream) {
+  return enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, dev_workspace, workspace_bytes, cfg,
                          static_cast<hipStream_t>(hip_stream), "decode_meshlets_batched");
 }
 
 extern "C" int gtsr_batched_graph_create(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
-                                         const gtsr_work_item* dev_work, uint32_t work_items,
-                                         const gtsr_launch_cfg* cfg, void** graph_exec) {
+                                         const gtsr_work_item* dev_work, uint32_t work_items, void* dev_workspace,
+                                         uint64_t workspace_bytes, uint32_t format, const gtsr_launch_cfg* cfg,
+                                         void** graph_exec) {
   const char* who = "gtsr_batched_graph_create";
   if (!graph_exec) return fail(GTSR_EINVAL, "gtsr_batched_graph_create: null graph_exec");
   *graph_exec = nullptr;
+  if (format != GTSR_FORMAT_REUSE && format != GTSR_FORMAT_GTS)
+    return fail(GTSR_EINVAL, "gtsr_batched_graph_create: bad format");
   hipStream_t s = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
     return fail(GTSR_EHIP, "gtsr_batched_graph_create: stream creation failed");
@@ -1024,7 +1118,8 @@ extern "C" int gtsr_batched_graph_create(const gtsr_mesh_entry* dev_mesh_table, 
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     rc = fail(GTSR_EHIP, "gtsr_batched_graph_create: begin capture failed");
   } else {
-    rc = enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, cfg, s, who);
+    rc = enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, dev_workspace, workspace_bytes, cfg, s,
+                         who, format == GTSR_FORMAT_GTS);
     hipError_t e = hipStreamEndCapture(s, &graph);
     if (rc == GTSR_OK && e != hipSuccess)
       rc = fail(GTSR_EHIP, std::string(who) + ": end capture: " + hipGetErrorString(e));

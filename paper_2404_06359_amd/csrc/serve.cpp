@@ -255,7 +255,7 @@ bool gtsr_server::admit_and_launch() {
   // reads them from host memory.
   const uint32_t rows = uint32_t(slot->reqs.size());
   hipError_t e = hipSuccess;
-  int rc = decode_meshlets_batched(slot->d_table, rows, slot->d_work, items, &p.cfg, slot->stream);
+  int rc = decode_meshlets_batched(slot->d_table, rows, slot->d_work, items, nullptr, 0, &p.cfg, slot->stream);
   if (rc == GTSR_OK) {
     e = hipEventRecord(slot->done, slot->stream);
     if (e != hipSuccess) rc = GTSR_EHIP;

@@ -76,3 +76,24 @@ def test_dequantize_full_size_sphere():
     say(f"[gpu] dequantize full-size sphere: {m.nverts} vertices")
     enc, q, ref = check(m, (64, 126), 16)
     assert ref.shape[0] == int(enc.vert_off[-1])
+
+
+def test_dequantize_offset_count_bounds_meshlets():
+    """Meshlets whose vertex range passes the offsets array's stated length
+    are skipped even when the output is large enough (the stated length
+    here is shorter than the real array, so every read stays in bounds)."""
+    m = meshgen.sphere(4, meshgen.rng_for(2, 13))
+    A = meshgen.vertex_attributes(m)
+    enc = P.encode(m.tri, m.nverts, 64, 126)
+    q = P.quantize_attributes(A, enc, 16)
+    ref = O.dequantize(O.Quantized(q.origin, q.delta, q.lowest, q.offsets), q.vert_off)
+    da = P.attrs_to_device(q)
+    half = int(q.vert_off[len(q.vert_off) // 2])
+    da.offset_count = half * 8 + 5            # not a whole vertex past the half: the next meshlet fails too
+    out = torch.full((int(q.vert_off[-1]), 8), -1.0, dtype=torch.float32, device="cuda")
+    say(f"[gpu] dequantize with offset_count {da.offset_count} of {q.offsets.size}")
+    P.dequantize(da, out=out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    np.testing.assert_array_equal(got[:half], ref[:half])
+    assert (got[half:] == -1.0).all()

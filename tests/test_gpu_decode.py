@@ -258,7 +258,8 @@ def test_batched_irregular_work_lists():
     for cfg in (None, {"waves_per_group": 1, "groups_per_cu": 1}, {"waves_per_group": 4, "groups_per_cu": 2}):
         say(f"[gpu] irregular work list cfg={cfg} items={n_items}")
         b.out_all.fill_(0xAA)
-        P._check(P.lib().decode_meshlets_batched(dtable.data_ptr(), 5, dwork.data_ptr(), n_items, P._cfg(cfg),
+        P._check(P.lib().decode_meshlets_batched(dtable.data_ptr(), 5, dwork.data_ptr(), n_items,
+                                                 b.workspace.data_ptr(), b.workspace.numel(), P._cfg(cfg),
                                                  P._stream_handle(None)))
         torch.cuda.synchronize()
         for i in range(4):
@@ -300,10 +301,16 @@ def test_autotune_picks_a_measured_shape_and_keeps_outputs():
     assert len(points) == 6
     assert {(p["target_tris"], p["waves_per_group"], p["groups_per_cu"], p["run_tris"]) for p in points} == \
         {(t, c["waves_per_group"], c["groups_per_cu"], c.get("run_tris", 0)) for t in (200, 3000) for c in cfgs}
-    assert best["median_ms"] == min(p["median_ms"] for p in points)
+    # the pick: among the finalists (measured again alone), the first in
+    # candidate order whose median is within 1 % of the fastest finalist's
+    fin = [p for p in points if p["stage"] == 2]
+    assert len(fin) == 4 and best in fin
+    band = np.float32(min(p["median_ms"] for p in fin)) * (np.float32(1.0) + np.float32(0.01))   # float32, as the tuner
+    assert best == next(p for p in fin if np.float32(p["median_ms"]) <= band)
+    assert all(p["median_ms"] > 0 for p in points)
     assert pool.work_items == best["work_items"]
     assert cfg == {"waves_per_group": best["waves_per_group"], "groups_per_cu": best["groups_per_cu"],
-                   "run_tris": best["run_tris"]}
+                   "run_tris": best["run_tris"], "items_per_claim": best["items_per_claim"]}
     for i, ref in enumerate(refs):
         np.testing.assert_array_equal(pool.output(i).cpu().numpy(), ref)
     pool.out.fill_(0x55)
@@ -362,6 +369,40 @@ def test_plain_gts_batched():
             torch.cuda.synchronize()
             for i, ref in enumerate(refs):
                 np.testing.assert_array_equal(pool.output(i).cpu().numpy(), ref)
+
+
+def test_plain_gts_batched_graph_and_autotune():
+    """Plain GTS pools take the same tuned, graph-captured path as GTS-Reuse
+    pools: the autotuner picks among plain-GTS shapes (the 1024-triangle tile
+    only), and every replay of the captured graph, with eager work and fills
+    between replays, decodes every mesh to the oracle's bytes."""
+    libencs = [P.gts_from_reuse(P.encode(m.tri, m.nverts, *caps)) for m, caps in _batched_meshes()]
+    refs = [O.decode_gts(O.GtsStream(e.desc_bytes, e.bits, e.reuse, e.strip_triangles)) for e in libencs]
+    pool = P.Pool(libencs)
+    say("[gpu] plain GTS autotune 2 targets x default shapes")
+    cfg, best, points = pool.autotune(targets=[300, 3000], reps=2)
+    # 9 static-split shapes (1024-triangle tile only) and 3 claiming shapes (default tile) per target
+    assert len(points) == 2 * 12
+    assert all(p["run_tris"] == 1024 for p in points if not p["items_per_claim"])
+    assert sorted(p["items_per_claim"] for p in points if p["items_per_claim"]) == [1, 1, 2, 2, 4, 4]
+    assert cfg["run_tris"] in (0, 1024)
+    for i, ref in enumerate(refs):
+        np.testing.assert_array_equal(pool.output(i).cpu().numpy(), ref)
+    g = pool.batched_graph(cfg)
+    for rep in range(4):
+        say(f"[gpu] plain GTS graph replay {rep}")
+        pool.out.fill_(0x55 if rep % 2 else 0xAA)
+        torch.cuda.synchronize()
+        g()
+        torch.cuda.synchronize()
+        for i, ref in enumerate(refs):
+            np.testing.assert_array_equal(pool.output(i).cpu().numpy(), ref)
+        x = torch.randn(1024, device="cuda").sum()
+        del x
+    # re-planning closes the graph: it held the old work list's address
+    pool.plan(700)
+    with pytest.raises(RuntimeError):
+        g()
 
 
 def assert_compact_parity(ds, full_ref, desc, cfgs, tag):

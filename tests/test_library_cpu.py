@@ -226,16 +226,16 @@ def test_launch_cfg_run_tris_validation():
     L = P.lib()
     for bad in (1, 768, 1152, 2048):
         c = P.LaunchCfg(0, 0, 0, bad)
-        assert L.decode_meshlets_batched(None, 0, None, 0, ctypes.byref(c), None) == P.EINVAL
+        assert L.decode_meshlets_batched(None, 0, None, 0, None, 0, ctypes.byref(c), None) == P.EINVAL
         assert "run_tris" in L.gtsr_last_error().decode()
     c = P.LaunchCfg(0, 0, 0, 1280)
-    assert L.gtsr_decode_gts_batched(None, 0, None, 0, ctypes.byref(c), None) == P.EINVAL
+    assert L.gtsr_decode_gts_batched(None, 0, None, 0, None, 0, ctypes.byref(c), None) == P.EINVAL
     empty = P.StreamDesc(None, None, None, 0, 0, 0, 0, 0)
     for tiles in (1024, 1280):
         c = P.LaunchCfg(0, 0, 0, tiles)
         assert L.gtsr_decode_meshlets_cfg(ctypes.byref(empty), None, 0, ctypes.byref(c), None) == P.EINVAL
         assert L.gtsr_decode_gts(ctypes.byref(empty), None, 0, ctypes.byref(c), None) == P.EINVAL
-        attrs = P.AttrStream(None, None, None, None, None, 1, 1)
+        attrs = P.AttrStream(None, None, None, None, None, 1, 1, 0)
         assert L.gtsr_dequantize(ctypes.byref(attrs), None, 0, ctypes.byref(c), None) == P.EINVAL
 
 
@@ -310,3 +310,23 @@ def test_library_cones_match_oracle(name, caps):
         dot = cl[:, :3].astype(np.float64) @ v.astype(np.float64)
         far = np.abs(dot - cl[:, 3]) > 1e-5
         np.testing.assert_array_equal(a[far], b[far])
+
+
+def test_claiming_needs_a_workspace_and_a_batched_decoder():
+    """items_per_claim is a batched-decoder knob: other decoders reject it,
+    and a claiming launch without a large enough, aligned workspace is
+    rejected before any device call."""
+    L = P.lib()
+    c = P.LaunchCfg(1, 0, 32, 0, 2)
+    ws = (ctypes.c_uint8 * 2048)()
+    base = ctypes.addressof(ws)
+    aligned = (base + 15) // 16 * 16
+    for workspace, nbytes in ((None, 0), (aligned, 512), (aligned + 2, 1024)):
+        assert L.decode_meshlets_batched(None, 0, None, 0, workspace, nbytes, ctypes.byref(c), None) == P.EINVAL
+        assert "workspace" in L.gtsr_last_error().decode()
+    empty = P.StreamDesc(None, None, None, 0, 0, 0, 0, 0)
+    assert L.gtsr_decode_meshlets_cfg(ctypes.byref(empty), None, 0, ctypes.byref(c), None) == P.EINVAL
+    assert "items_per_claim" in L.gtsr_last_error().decode()
+    big = P.LaunchCfg(1, 0, 32, 0, 1025)
+    assert L.decode_meshlets_batched(None, 0, None, 0, aligned, 1024, ctypes.byref(big), None) == P.EINVAL
+    assert P.BATCHED_WORKSPACE_BYTES == 1024
