@@ -345,6 +345,27 @@ int gtsr_decode_gts_batched(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh
                             const gtsr_work_item* dev_work, uint32_t work_items, void* dev_workspace,
                             uint64_t workspace_bytes, const gtsr_launch_cfg* cfg, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * decode_meshlets_batched in its claiming mode with the claim counters in a
+ * static device array of the library's own instead of a caller workspace.
+ * The array is GTSR_BATCHED_WORKSPACE_BYTES (1 KiB: one 32-bit counter per
+ * XCD, one per 128-byte line), its size fixed whatever the input (the input
+ * limits are those of decode_meshlets_batched: at most 2^31 work items), and
+ * each device holds one copy until the process ends.  Its address is looked
+ * up once per device, on the first call with that device current.  A small
+ * kernel enqueued in front of the decode zeroes the counters, so each call
+ * starts clean; calls that overlap on one device share the array and race,
+ * so enqueue them on one stream (or ordered streams).  format:
+ * GTSR_FORMAT_REUSE or GTSR_FORMAT_GTS; cfg as for decode_meshlets_batched
+ * (NULL or items_per_claim 0 = 2 items per claim; groups_per_cu 0 = 32 /
+ * waves_per_group).  Calls no hipMalloc, hipFree or other allocating
+ * routine; enqueued on hip_stream.  Errors: as decode_meshlets_batched, and
+ * EHIP if the array's address cannot be found. */
+int gtsr_decode_batched_noalloc(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
+                                const gtsr_work_item* dev_work, uint32_t work_items, uint32_t format,
+                                const gtsr_launch_cfg* cfg, void* hip_stream);
+
 /* Capture one batched decode into an executable HIP graph once (its kernel
  * node, and with cfg->items_per_claim > 0 the counter-zeroing kernel node in
  * front of it); *graph_exec receives the handle.  format: GTSR_FORMAT_REUSE

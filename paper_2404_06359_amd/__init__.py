@@ -31,7 +31,7 @@ EXPORTED = (
     "gtsr_server_get_stats", "gtsr_server_replay", "gtsr_server_destroy",
     "gtsr_gts_from_reuse", "gtsr_decode_gts", "gtsr_decode_gts_batched", "gtsr_decode_compact",
     "gtsr_quantize_attributes", "gtsr_dequantize", "gtsr_min_strips", "gtsr_meshlet_cones",
-    "gtsr_decode_culled", "gtsr_stream_calib",
+    "gtsr_decode_culled", "gtsr_stream_calib", "gtsr_decode_batched_noalloc",
 )
 
 
@@ -171,6 +171,7 @@ def lib():
         "gtsr_decode_culled": (C.c_int, [C.POINTER(StreamDesc), vp, C.c_float, C.c_float, C.c_float, vp, u64,
                                          C.POINTER(LaunchCfg), vp]),
         "gtsr_stream_calib": (C.c_int, [vp, u64, vp, u64, C.POINTER(LaunchCfg), C.POINTER(u64), vp]),
+        "gtsr_decode_batched_noalloc": (C.c_int, [vp, u32, vp, u32, u32, C.POINTER(LaunchCfg), vp]),
     }
     for name, (rt, args) in sig.items():
         f = getattr(L, name)

@@ -1147,3 +1147,50 @@ extern "C" void gtsr_graph_destroy(void* graph_exec) {
 }
 
 extern "C" uint32_t gtsr_device_cu_count(void) { return cu_count(); }
+
+// ------------------------------------------------- allocation-free entry point
+
+// The claim counters of gtsr_decode_batched_noalloc: a file-scope device
+// array, one copy per device the library runs on, kept until the process
+// ends.  In host code its name is not a device address; each device's
+// address comes from hipGetSymbolAddress on that call's first use of the
+// device, with the device current, and is kept per device.
+static __device__ __align__(256) uint32_t scratch[GTSR_BATCHED_WORKSPACE_BYTES / 4];
+
+namespace gtsr {
+namespace {
+constexpr uint32_t kScratchBytes = GTSR_BATCHED_WORKSPACE_BYTES;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices];
+
+int scratch_ptr(void** out, const char* who) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(GTSR_EHIP, std::string(who) + ": cannot query the device");
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GTSR_EHIP, std::string(who) + ": scratch address: " + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GTSR_OK;
+}
+}  // namespace
+}  // namespace gtsr
+
+extern "C" int gtsr_decode_batched_noalloc(const gtsr_mesh_entry* dev_mesh_table, uint32_t mesh_count,
+                                           const gtsr_work_item* dev_work, uint32_t work_items, uint32_t format,
+                                           const gtsr_launch_cfg* cfg, void* hip_stream) {
+  const char* who = "gtsr_decode_batched_noalloc";
+  if (format != GTSR_FORMAT_REUSE && format != GTSR_FORMAT_GTS) return fail(GTSR_EINVAL, std::string(who) + ": bad format");
+  gtsr_launch_cfg c{};
+  if (cfg) c = *cfg;
+  if (!c.items_per_claim) c.items_per_claim = 2;
+  void* ws = nullptr;
+  if (int rc = scratch_ptr(&ws, who)) return rc;
+  return enqueue_batched(dev_mesh_table, mesh_count, dev_work, work_items, ws, kScratchBytes, &c,
+                         static_cast<hipStream_t>(hip_stream), who, format == GTSR_FORMAT_GTS);
+}
