@@ -37,7 +37,7 @@ _lib_lock = threading.Lock()
 
 def build() -> str:
     """Compile ``meshgen.c`` (plain C, gcc) into ``libmeshgen.so``."""
-    tmp = LIB_PATH + ".tmp"
+    tmp = f"{LIB_PATH}.{os.getpid()}.tmp"   # private per process: test workers may build at once
     subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-o", tmp,
                     os.path.join(HERE, "meshgen.c"), "-lm"], check=True)
     os.replace(tmp, LIB_PATH)
@@ -49,9 +49,9 @@ def build_sanitized() -> str:
     (gcc), into ``_build/sanitize/libmeshgen.so``, for CPU test runs."""
     os.makedirs(os.path.dirname(SANITIZED_PATH), exist_ok=True)
     subprocess.run(["gcc", "-O1", "-g", "-std=c99", "-Wall", "-shared", "-fPIC", "-fsanitize=address,undefined",
-                    "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-o", SANITIZED_PATH + ".tmp",
+                    "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-o", f"{SANITIZED_PATH}.{os.getpid()}.tmp",
                     os.path.join(HERE, "meshgen.c"), "-lm"], check=True)
-    os.replace(SANITIZED_PATH + ".tmp", SANITIZED_PATH)
+    os.replace(f"{SANITIZED_PATH}.{os.getpid()}.tmp", SANITIZED_PATH)
     return SANITIZED_PATH
 
 

@@ -31,7 +31,7 @@ _lib = None
 def build() -> str:
     """Compile ``oracle.c`` into ``liboracle.so`` (gcc, plain -O2)."""
     src = os.path.join(HERE, "oracle.c")
-    tmp = LIB_PATH + ".tmp"
+    tmp = f"{LIB_PATH}.{os.getpid()}.tmp"   # private per process: test workers may build at once
     subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
                     "-o", tmp, src, "-lm"], check=True)
     os.replace(tmp, LIB_PATH)
@@ -44,8 +44,8 @@ def build_sanitized() -> str:
     os.makedirs(os.path.dirname(SANITIZED_PATH), exist_ok=True)
     subprocess.run(["gcc", "-O1", "-g", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
                     "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
-                    "-o", SANITIZED_PATH + ".tmp", os.path.join(HERE, "oracle.c"), "-lm"], check=True)
-    os.replace(SANITIZED_PATH + ".tmp", SANITIZED_PATH)
+                    "-o", f"{SANITIZED_PATH}.{os.getpid()}.tmp", os.path.join(HERE, "oracle.c"), "-lm"], check=True)
+    os.replace(f"{SANITIZED_PATH}.{os.getpid()}.tmp", SANITIZED_PATH)
     return SANITIZED_PATH
 
 

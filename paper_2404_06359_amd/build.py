@@ -56,7 +56,7 @@ def build(verbose: bool = False) -> str:
         for r in ex.map(_run, jobs):
             if verbose and (r.stdout or r.stderr):
                 sys.stderr.write(r.stdout + r.stderr)
-    tmp = LIB + ".tmp"
+    tmp = f"{LIB}.{os.getpid()}.tmp"   # private per process: test workers may build at once
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
@@ -91,8 +91,8 @@ def build_sanitized(verbose: bool = False) -> str:
                 sys.stderr.write(r.stdout + r.stderr)
     out = os.path.join(SANITIZE_DIR, "libgtsr.so")
     _run([CXX, "-shared", "-fPIC", "-pthread", *SANITIZE, *objs, "-L/opt/rocm/lib", "-lamdhip64",
-          "-Wl,-rpath,/opt/rocm/lib", "-o", out + ".tmp"])
-    os.replace(out + ".tmp", out)
+          "-Wl,-rpath,/opt/rocm/lib", "-o", f"{out}.{os.getpid()}.tmp"])
+    os.replace(f"{out}.{os.getpid()}.tmp", out)
     return out
 
 

@@ -28,8 +28,10 @@ def _asan_runtime():
 
 def _env(asan):
     env = dict(os.environ)
+    # the sanitizer runtime goes first; libraries already preloaded stay after it
+    preload = asan + (":" + env["LD_PRELOAD"] if env.get("LD_PRELOAD") else "")
     env.update({
-        "LD_PRELOAD": asan,
+        "LD_PRELOAD": preload,
         "ASAN_OPTIONS": "detect_leaks=0:halt_on_error=1:abort_on_error=1",
         "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1",
         "GTSR_LIBRARY": os.path.join(ROOT, "_build", "sanitize", "libgtsr.so"),
