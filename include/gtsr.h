@@ -15,7 +15,7 @@
  *     on the GPU back to 8-bit local index triples.
  *
  * encode_meshlets is the CPU side; decode_meshlets (one mesh) and
- * decode_meshlets_batched (many meshes, one persistent launch) are the GPU
+ * decode_meshlets_batched (many meshes, one launch) are the GPU
  * side.  Every call returns an int status (GTSR_OK or a negative code); no
  * exception crosses this interface.  gtsr_last_error() describes the last
  * failure on the calling thread.  All calls are reentrant.
@@ -51,7 +51,9 @@ enum {
   GTSR_EDEGENERATE = -3,  /* an input triangle repeats a vertex */
   GTSR_ELIMIT = -4,       /* caps out of range, or counts overflow 32-bit offsets */
   GTSR_ECORRUPT = -5,     /* gtsr_validate found a violated stream invariant */
-  GTSR_EHIP = -6          /* a HIP runtime call failed */
+  GTSR_EHIP = -6,         /* a HIP runtime call failed */
+  GTSR_ECANCELED = -7,    /* serving: the request was withdrawn before admission */
+  GTSR_EBUSY = -8         /* serving: too late to withdraw, the request was already admitted */
 };
 
 /* Stream formats (Sec. 4.2 / 4.3; Fig. "Strip Encoding" (c) and (d)). */
@@ -205,15 +207,22 @@ int encode_meshlets(const uint32_t* indices, uint64_t triangle_count, uint32_t v
 int gtsr_min_strips(const uint32_t* indices, uint32_t triangle_count, uint64_t node_limit, uint32_t* strips,
                     uint32_t* proven);
 
-/* Fill *view with pointers into e.  Errors: EINVAL on null. */
+/* Fill *view with pointers into e: the meshlets of Sec. 3 (descriptors,
+ * local-to-global vertex lists), the GTS-Reuse streams of Sec. 4.2 / 4.3
+ * (flag chunks, reuse bytes) and the encoder's counters (restarts: Sec. 4.2's
+ * four degenerates each; payload bits as in Table 2).  Errors: EINVAL on
+ * null. */
 int gtsr_encoded_view_get(const gtsr_encoded* e, gtsr_encoded_view* view);
 
 void gtsr_encoded_free(gtsr_encoded* e);
 
-/* Full structural check of a host-resident stream: counts in range,
- * contiguous offsets from 0, array sizes equal to the totals, triangle 0's INC
- * bit and all bits past T_s clear, increments = V - 3, reuse bytes naming
- * vertices already introduced.  Returns OK or ECORRUPT (EINVAL on null). */
+/* Full structural check of a host-resident stream against the invariants of
+ * Sec. 4.3 (vertices renumbered by first appearance: the strip starts with
+ * 0, 1, 2, every increment flag introduces the next vertex, every reuse byte
+ * names one already introduced) and of the layout above: counts in range
+ * (Sec. 3's caps, T_s <= 256), contiguous offsets from 0, array sizes equal
+ * to the totals, triangle 0's INC bit and all bits past T_s clear,
+ * increments = V - 3.  Returns OK or ECORRUPT (EINVAL on null). */
 int gtsr_validate(const gtsr_stream* host_stream);
 
 /* Re-encode a valid host GTS-Reuse stream as plain GTS (same strips, same
@@ -225,7 +234,9 @@ int gtsr_validate(const gtsr_stream* host_stream);
 int gtsr_gts_from_reuse(const gtsr_stream* host_reuse_stream, gtsr_meshlet* gdesc, uint8_t* words,
                         uint64_t words_bytes, uint8_t* index, uint64_t index_bytes);
 
-/* Build a triangle-balanced work list for decode_meshlets_batched.
+/* Build a triangle-balanced work list for decode_meshlets_batched (not in
+ * the paper, which dispatches one thread group per meshlet (Sec. 3); the
+ * batched decoders hand a wavefront a run of consecutive meshlets instead).
  * host_meshlets[i] points at mesh i's host descriptor array of
  * meshlet_counts[i] entries.  Items never span two meshes and hold
  * consecutive meshlets totalling about target_tris strip triangles (at
@@ -410,9 +421,11 @@ typedef struct gtsr_tune_point {
  * every candidate in turn, 4 launches each, with HIP events between
  * candidates and no host wait inside a stage, so the device never idles
  * while measuring; a candidate's figure is the median over rounds of its
- * per-launch time.  The 4 fastest are measured again alone over 3 * reps
- * rounds; among them the first in candidate order (list-major) whose median
- * is within 1 % of the fastest is *best (target_tris holds its list index).
+ * per-launch time.  The finalists -- the 4 fastest, and any others within
+ * 2 % of the fastest, at most 8 in all -- are measured again alone over
+ * 3 * reps rounds; among them the first in candidate order (list-major) whose
+ * median is within 1 % of the fastest is *best (target_tris holds its list
+ * index).
  * points (may be NULL) receives up to capacity points, one per candidate in
  * candidate order (the finalists' figures from the second stage), and
  * *point_count (may be NULL) the number of candidates.  Synchronous:
@@ -469,6 +482,8 @@ typedef struct gtsr_server_stats {
   uint64_t submitted, completed, batches, max_batch_seen;
   uint64_t strip_triangles;  /* decoded by completed requests */
   uint64_t max_arena_used, arena_used, pending;
+  uint64_t cancelled;        /* withdrawn by gtsr_server_cancel */
+  uint64_t failed;           /* completed with an error status */
 } gtsr_server_stats;
 
 /* host_table: host copy of the pool's mesh table (device stream pointers;
@@ -497,6 +512,14 @@ int gtsr_server_poll(gtsr_server* server, gtsr_completion* out, uint32_t capacit
 /* Give a finished request's arena range back to the budget; the output may
  * be overwritten afterwards.  Errors: EINVAL (unknown tag, still decoding). */
 int gtsr_server_release(gtsr_server* server, uint64_t tag);
+
+/* Withdraw a request that has not been admitted yet: it leaves the queue, so
+ * the requests behind it (which first-come first-served admission holds
+ * back while it does not fit) may go ahead; poll reports it with status
+ * ECANCELED and no output; its tag is free at once (no release).
+ * Thread-safe.  Errors: EBUSY (already admitted: it completes normally and
+ * is released as usual), EINVAL (no request with this tag). */
+int gtsr_server_cancel(gtsr_server* server, uint64_t tag);
 
 int gtsr_server_get_stats(gtsr_server* server, gtsr_server_stats* stats);
 
@@ -581,7 +604,7 @@ int gtsr_graph_launch(void* graph_exec, void* hip_stream);
 
 void gtsr_graph_destroy(void* graph_exec);
 
-/* Compute units of the current device, as the decoders size persistent
+/* Compute units of the current device, as the decoders size their
  * grids.  Returns 0 on error. */
 uint32_t gtsr_device_cu_count(void);
 

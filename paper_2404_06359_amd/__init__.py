@@ -19,7 +19,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 # one for CPU test runs); by default the in-tree build is loaded.
 LIB_PATH = os.environ.get("GTSR_LIBRARY") or os.path.join(PKG, "libgtsr.so")
 
-OK, EINVAL, ENOMEM, EDEGENERATE, ELIMIT, ECORRUPT, EHIP = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EDEGENERATE, ELIMIT, ECORRUPT, EHIP, ECANCELED, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FORMAT_REUSE, FORMAT_GTS = 0, 1
 
 EXPORTED = (
@@ -27,7 +27,7 @@ EXPORTED = (
     "gtsr_plan_batch", "decode_meshlets", "gtsr_decode_meshlets_cfg", "gtsr_decode_meshlets_many",
     "decode_meshlets_batched", "gtsr_batched_graph_create", "gtsr_graph_launch",
     "gtsr_graph_destroy", "gtsr_device_cu_count", "gtsr_last_error", "gtsr_autotune_batched",
-    "gtsr_server_create", "gtsr_server_submit", "gtsr_server_poll", "gtsr_server_release",
+    "gtsr_server_create", "gtsr_server_submit", "gtsr_server_poll", "gtsr_server_release", "gtsr_server_cancel",
     "gtsr_server_get_stats", "gtsr_server_replay", "gtsr_server_destroy",
     "gtsr_gts_from_reuse", "gtsr_decode_gts", "gtsr_decode_gts_batched", "gtsr_decode_compact",
     "gtsr_quantize_attributes", "gtsr_dequantize", "gtsr_min_strips", "gtsr_meshlet_cones",
@@ -106,7 +106,8 @@ class ServerParams(C.Structure):
 
 class ServerStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "batches", "max_batch_seen",
-                                           "strip_triangles", "max_arena_used", "arena_used", "pending")]
+                                           "strip_triangles", "max_arena_used", "arena_used", "pending",
+                                           "cancelled", "failed")]
 
 
 COMPLETION_DTYPE = np.dtype([("tag", "<u8"), ("mesh", "<u4"), ("status", "<i4"), ("out_offset", "<u8"),
@@ -157,6 +158,7 @@ def lib():
         "gtsr_server_submit": (C.c_int, [vp, u32, u64]),
         "gtsr_server_poll": (C.c_int, [vp, vp, u32, C.POINTER(u32), u32]),
         "gtsr_server_release": (C.c_int, [vp, u64]),
+        "gtsr_server_cancel": (C.c_int, [vp, u64]),
         "gtsr_server_get_stats": (C.c_int, [vp, C.POINTER(ServerStats)]),
         "gtsr_server_replay": (C.c_int, [vp, vp, vp, u32, u64, vp, C.POINTER(u64)]),
         "gtsr_server_destroy": (None, [vp]),
@@ -447,7 +449,7 @@ def decode_compact(ds: DeviceStream, kept_off, out=None, stream=None, cfg=None):
 
 
 class Batch:
-    """Many device-resident meshes decoded by one persistent launch.
+    """Many device-resident meshes decoded by one batched launch.
 
     Holds the device mesh table, the work list and one output
     tensor per mesh (views into a single allocation)."""
@@ -739,6 +741,16 @@ class Server:
 
     def release(self, tag: int):
         _check(lib().gtsr_server_release(self._h, int(tag)))
+
+    def cancel(self, tag: int) -> bool:
+        """Withdraw a request not yet admitted (``gtsr_server_cancel``): True if
+        it left the queue (poll reports it with status ``ECANCELED``), False if
+        it was already admitted and completes normally."""
+        rc = lib().gtsr_server_cancel(self._h, int(tag))
+        if rc == EBUSY:
+            return False
+        _check(rc)
+        return True
 
     def stats(self) -> dict:
         st = ServerStats()

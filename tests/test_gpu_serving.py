@@ -147,3 +147,46 @@ def test_server_arena_units(pool):
     out = drain(srv, 1)
     np.testing.assert_array_equal(out[1], refs[i])
     srv.close()
+
+
+def test_cancel_unblocks_the_queue(pool):
+    """A request that does not fit blocks the ones behind it until it is
+    withdrawn: cancelling it lets the next request through, reports it with
+    ECANCELED, and a request already admitted cannot be withdrawn."""
+    pool_, refs = pool
+    big = int(np.argmax([r.nbytes for r in refs]))
+    small = int(np.argmin([r.nbytes if r.nbytes else 1 << 60 for r in refs]))
+    span = lambda n: max(256, (n + 255) // 256 * 256)
+    srv = P.Server(pool_, arena_bytes=span(refs[big].nbytes) + span(refs[small].nbytes), max_inflight=2)
+    srv.submit(big, 1)
+    first = []
+    t_end = time.time() + 30
+    while not first:
+        assert time.time() < t_end
+        first = list(srv.poll(timeout_us=1000))
+    assert int(first[0]["tag"]) == 1 and first[0]["status"] == 0
+    np.testing.assert_array_equal(srv.output(first[0]).cpu().numpy(), refs[big])
+    srv.submit(big, 2)      # cannot fit while request 1 holds its range
+    srv.submit(small, 3)    # would fit, but waits behind request 2
+    assert len(srv.poll(timeout_us=20000)) == 0
+    assert srv.stats()["pending"] == 2
+    assert srv.cancel(1) is False           # admitted (finished, unreleased)
+    assert srv.cancel(2) is True
+    with pytest.raises(P.GtsrError) as e:
+        srv.cancel(2)
+    assert e.value.code == P.EINVAL
+    got = {}
+    t_end = time.time() + 30
+    while len(got) < 2:
+        assert time.time() < t_end
+        for c in srv.poll(timeout_us=1000):
+            got[int(c["tag"])] = c
+            if c["status"] == 0:
+                np.testing.assert_array_equal(srv.output(c).cpu().numpy(), refs[small])
+    assert got[2]["status"] == P.ECANCELED and got[2]["out_bytes"] == 0
+    assert got[3]["status"] == 0
+    for t in (1, 3):
+        srv.release(t)
+    st = srv.stats()
+    assert st["cancelled"] == 1 and st["completed"] == 2 and st["failed"] == 0 and st["arena_used"] == 0
+    srv.close()
