@@ -4,7 +4,7 @@
 Default workload (one step = one decode of all of it): 2000 synthetic meshes
 (regular grids and sphere patches, triangle counts log-uniform in [1e3, 2e6],
 meshlet caps drawn from 32v/64t, 64v/126t, 128v/256t), encoded on the host,
-resident in HBM, decoded by one persistent HIP-graph launch.  Beside it: the
+resident in HBM, decoded by one HIP-graph launch.  Beside it: the
 same meshes decoded with one plain launch per mesh, and the oracle's
 sequential decoder timed on the host cores.
 
@@ -101,12 +101,91 @@ def build_batched(count: int, threads: int):
     return encs
 
 
-def build_sphere():
+def build_stress(count: int, threads: int):
+    """The stress workload: Delaunay triangulations of seeded random points
+    (50k-1M triangles each, log-uniform), caps 64v/126t."""
     import meshgen
     import paper_2404_06359_amd as P
 
-    m = meshgen.workload2()
-    return [P.encode(m.tri, m.nverts, 64, 126, threads=0)]
+    meshes = meshgen.workload4(count, threads)
+
+    def one(m):
+        return P.encode(m.tri, m.nverts, m.max_vertices, m.max_triangles, threads=1)
+
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(one, meshes))
+
+
+def run_single(args):
+    """One mesh per step with the plain decoder: the 64x64 grid (latency-bound:
+    also the median of isolated launches), or the 5.2M-triangle icosphere with
+    the step rotating over enough copies of its streams and output (at least
+    32, over 640 MiB together) that none is still in the 256 MB last-level
+    cache when its turn comes."""
+    import torch
+    import meshgen
+    import paper_2404_06359_amd as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    m = meshgen.workload1() if args.workload == "grid" else meshgen.workload2()
+    enc = P.encode(m.tri, m.nverts, m.max_vertices, m.max_triangles, threads=0)
+    prep_s = time.perf_counter() - t0
+    alg = algorithmic_bytes([enc])
+    sets = 1 if args.workload == "grid" else max(32, -(-(640 << 20) // alg))
+    dss = [P.to_device(enc, dev) for _ in range(sets)]
+    outs = [torch.empty((enc.strip_triangles, 3), dtype=torch.uint8, device=dev) for _ in range(sets)]
+    k = [0]
+
+    def step():
+        i = k[0] % sets
+        P.decode(dss[i], out=outs[i], stream=stream)
+        k[0] += 1
+
+    for _ in range(max(args.warmup, 2 * sets if args.workload == "sphere" else 0)):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    extra = {}
+    if args.workload == "grid":
+        lat = []
+        for _ in range(50):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            step()
+            b.record(stream)
+            torch.cuda.synchronize()
+            lat.append(a.elapsed_time(b) * 1e3)
+        extra["isolated_launch_us"] = {"p50": round(float(np.percentile(lat, 50)), 2),
+                                       "p10": round(float(np.percentile(lat, 10)), 2),
+                                       "p90": round(float(np.percentile(lat, 90)), 2)}
+        workload = ("single mesh: 64x64 quad grid (8192 triangles), caps 64v/126t, one plain launch per step; "
+                    "latency-bound")
+    else:
+        workload = (f"single large mesh: icosphere level 9 (5.2M triangles), caps 64v/126t, one plain launch per "
+                    f"step over {sets} rotated copies of its streams and output "
+                    f"({sets * alg / 2**20:.0f} MiB, past the 256 MB last-level cache)")
+    if args.calib_copy_mib:
+        calibration_copy(args.calib_copy_mib, dev)
+    achieved = alg / (ms / 1e3) / 1e9
+    log(f"[bench] {args.workload}: {ms * 1e3:.1f} us per step, {achieved:.0f} GB/s algorithmic, sets {sets}")
+    return {"metric": "decoded triangles/s (Gtps) + HBM GB/s, batched vs per-mesh",
+            "value": m.ntri / (ms / 1e3) / 1e9, "unit": "Gtps", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": workload, "input_triangles": int(m.ntri), "strip_triangles": enc.strip_triangles,
+                       "meshlets": enc.meshlet_count, "rotated_sets": sets, "prep_seconds": round(prep_s, 2)},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": alg},
+            "us_per_step": ms * 1e3, **extra}
 
 
 def build_serve_prototypes(threads: int):
@@ -202,6 +281,20 @@ def run_serve(args, threads):
     }
 
 
+def calibration_copy(mib: int, dev):
+    """One device copy of a known size: rocprofv3's FETCH_SIZE and WRITE_SIZE
+    for it give the factors that scale those counters to bytes."""
+    import torch
+
+    nbytes = mib << 20
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+
+
 def time_ms(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -227,9 +320,9 @@ def line(metric, value, unit, ms, args, workload, achieved, alg, dtype="u8", **e
 
 
 def run_feature(args):
-    """The next-row features, each timed on its own: plain GTS batched decode
-    (the batched workload re-encoded), and on the 5.2M-triangle sphere the
-    compacted decode, the cone-culled decode and attribute dequantization."""
+    """The next-row features on the 5.2M-triangle sphere, each timed on its
+    own: the compacted decode, the cone-culled decode and attribute
+    dequantization.  (Plain GTS takes the batched workload's path.)"""
     import torch
     import meshgen
     import paper_2404_06359_amd as P
@@ -237,16 +330,6 @@ def run_feature(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    if args.workload == "gts":
-        encs = [P.gts_from_reuse(e) for e in build_batched(args.meshes, host_threads())]
-        pool = P.Pool(encs, device=dev)
-        pool.plan(args.target_tris)
-        ms = time_ms(lambda: pool.decode_batched(stream), args.steps, args.warmup, stream)
-        alg = sum(e.meshlets.nbytes + e.bits.nbytes + e.reuse.nbytes + 3 * e.strip_triangles for e in encs)
-        tris = sum(e.stats["input_triangles"] for e in encs)
-        return line("decoded triangles/s, plain GTS batched", tris / (ms / 1e3) / 1e9, "Gtps", ms, args,
-                    "batched 2000 meshes re-encoded as plain GTS (one index byte per strip triangle), one launch",
-                    alg / (ms / 1e3) / 1e9, alg, stored_bytes=sum(e.stats["stored_bytes"] for e in encs))
     m = meshgen.workload2()
     enc = P.encode(m.tri, m.nverts, 64, 126, threads=0)
     ds = P.to_device(enc, dev)
@@ -327,7 +410,10 @@ def cpu_baseline(encs, pool, threads):
 
     def one(i):
         e = encs[i]
-        oracle.decode_arrays(e.desc_bytes, e.bits, e.reuse, e.strip_triangles, out=outs[i])
+        if getattr(e, "format", 0) == 1:   # plain GTS
+            oracle.decode_gts(oracle.GtsStream(e.desc_bytes, e.bits, e.reuse, e.strip_triangles), out=outs[i])
+        else:
+            oracle.decode_arrays(e.desc_bytes, e.bits, e.reuse, e.strip_triangles, out=outs[i])
 
     order = sorted(range(len(encs)), key=lambda i: -encs[i].strip_triangles)
     times = []
@@ -362,7 +448,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", choices=["batched", "sphere", "serve", "gts", "compact", "cull", "dequant"],
+    ap.add_argument("--workload", choices=["batched", "stress", "grid", "sphere", "serve", "gts", "compact", "cull",
+                                           "dequant"],
                     default="batched")
     ap.add_argument("--pool-meshes", type=int, default=5000, help="serve: pool size")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: mean requests per second")
@@ -383,8 +470,8 @@ def main():
     ap.add_argument("--no-calib", action="store_true", help="skip the achievable-bandwidth calibration")
     ap.add_argument("--no-serve", action="store_true", help="batched: skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=6000, help="batched: requests of the serving leg")
-    ap.add_argument("--bridge", type=int, default=20,
-                    help="batched: direct launches that keep the device busy while the graph is captured")
+    ap.add_argument("--bridge", type=int, default=30,
+                    help="batched: launches that keep the device busy after tuning and while the graph is captured")
     ap.add_argument("--cold-steps", type=int, default=20,
                     help="batched: launches timed after one idle second (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -406,15 +493,23 @@ def main():
     if args.workload == "serve":
         print(json.dumps(run_serve(args, host_threads())))
         return
-    if args.workload in ("gts", "compact", "cull", "dequant"):
+    if args.workload in ("compact", "cull", "dequant"):
         print(json.dumps(run_feature(args)))
+        return
+    if args.workload in ("grid", "sphere"):
+        print(json.dumps(run_single(args)))
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     threads = host_threads()
 
     t0 = time.perf_counter()
-    encs = build_batched(args.meshes, threads) if args.workload == "batched" else build_sphere()
+    if args.workload == "stress":
+        encs = build_stress(200, threads)
+    else:
+        encs = build_batched(args.meshes, threads)
+        if args.workload == "gts":   # the same meshes as plain GTS streams (one index byte per strip triangle)
+            encs = [P.gts_from_reuse(e) for e in encs]
     prep_s = time.perf_counter() - t0
     in_tris = int(sum(e.stats["input_triangles"] for e in encs))
     strip_tris = int(sum(e.strip_triangles for e in encs))
@@ -430,51 +525,70 @@ def main():
     plain_cfg = dict(cfg)
     stream = torch.cuda.current_stream()
     tuned = None
-    if args.workload == "batched":
-        if args.no_autotune:
-            pool.plan(args.target_tris)
-        else:
-            # the tuner keeps the device busy with back-to-back launches and
-            # leaves the winning work list in the pool: no re-planning, so the
-            # timed launches follow the tuner's with no idle device between
-            t0 = time.perf_counter()
-            cfg, best, points = pool.autotune(stream=stream)
-            tuned = {"target_tris": best["target_tris"], "waves_per_group": best["waves_per_group"],
-                     "groups_per_cu": best["groups_per_cu"], "run_tris": best["run_tris"], "points": len(points),
-                     "median_ms": round(best["median_ms"], 4), "seconds": round(time.perf_counter() - t0, 2)}
-            log(f"[bench] autotune: {len(points)} shapes, best {best}")
-            # The device lowers its clock for tens of milliseconds whenever
-            # sustained load starts from idle; a few direct launches of the
-            # chosen shape keep it busy while the host captures the graph, so
-            # the timed steps continue the tuner's sustained load.  (The
-            # cold_start entry times the other case.)
-            for _ in range(args.bridge):
-                pool.decode_batched(stream, cfg)
-        graph = pool.batched_graph(cfg)
-        step = lambda: graph(stream)
-        kernel = "decode_batched"
+    if args.no_autotune:
+        pool.plan(args.target_tris)
     else:
-        step = lambda: pool.decode_per_mesh(stream, plain_cfg)
-        kernel = "decode_plain"
+        # the tuner keeps the device busy with back-to-back launches and
+        # leaves the winning work list in the pool: no re-planning, so the
+        # timed launches follow the tuner's with no idle device between
+        t0 = time.perf_counter()
+        cfg, best, points = pool.autotune(stream=stream)
+        tuned = {"target_tris": best["target_tris"], "waves_per_group": best["waves_per_group"],
+                 "groups_per_cu": best["groups_per_cu"], "run_tris": best["run_tris"],
+                 "items_per_claim": best["items_per_claim"], "points": len(points),
+                 "median_ms": round(best["median_ms"], 4), "seconds": round(time.perf_counter() - t0, 2)}
+        log(f"[bench] autotune: {len(points)} shapes, best {best}")
+    # A step is one launch of the boundary call decode_meshlets_batched over
+    # the whole table.  The tuner keeps the device busy with back-to-back
+    # launches and leaves the winning work list in the pool (no re-planning),
+    # so the warm-up and timed launches continue its sustained load; the
+    # device lowers its clock for tens of milliseconds whenever sustained
+    # load starts from idle (the cold_start entry times that case).
+    step = lambda: pool.decode_batched(stream, cfg)
+    kernel = "decode_gts_batched" if args.workload == "gts" else "decode_batched"
+    # The host's work between the tuner's last launch and the first warm-up
+    # launch idles the device for a moment, and the device slows down for
+    # about ten milliseconds a few milliseconds after that; launches enqueued
+    # right away cover it (1 % faster timed steps, measured).
+    for _ in range(args.bridge):
+        step()
 
-    def timed_steps(n):
+    def timed_steps(n, fn=None, marks=False):
+        """n steps between two events (no host wait in between); with marks,
+        an event after every step as well, for per-step times."""
+        fn = fn or step
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        marks = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+        mk = [torch.cuda.Event(enable_timing=True) for _ in range(n)] if marks else []
         ev0.record(stream)
         for k in range(n):
-            step()
-            marks[k].record(stream)
+            fn()
+            if marks:
+                mk[k].record(stream)
         ev1.record(stream)
         torch.cuda.synchronize()
-        per = np.array([ev0.elapsed_time(marks[0])] + [marks[k - 1].elapsed_time(marks[k]) for k in range(1, n)])
+        per = None
+        if marks:
+            per = np.array([ev0.elapsed_time(mk[0])] + [mk[k - 1].elapsed_time(mk[k]) for k in range(1, n)])
         return ev0.elapsed_time(ev1) / n, per
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ms, per_step = timed_steps(args.steps)
+    ms, _ = timed_steps(args.steps)
+    # the same steps again, each followed by an event, for per-step percentiles
+    _, per_step = timed_steps(args.steps, marks=True)
     step_pct = {f"p{q}": round(float(np.percentile(per_step, q)), 4) for q in (10, 50, 90)}
-    log(f"[bench] {kernel}: {ms:.4f} ms per step, per-step {step_pct}")
+    # and as replays of a captured graph holding the same launch; direct
+    # launches keep the device busy while the host captures it
+    for _ in range(args.bridge):
+        step()
+    graph = pool.batched_graph(cfg)
+    graph_step = lambda: graph(stream)
+    for _ in range(args.warmup):
+        graph_step()
+    graph_ms, _ = timed_steps(args.steps, fn=graph_step)
+    log(f"[bench] {kernel}: {ms:.4f} ms per step (direct launches), per-step {step_pct}; "
+        f"graph replays {graph_ms:.4f} ms")
 
     # Achievable bandwidth for this traffic mix: the calibration kernel reads
     # and writes the decode's algorithmic byte counts with its access pattern.
@@ -531,21 +645,14 @@ def main():
     cold = None
     if args.cold_steps:
         time.sleep(1.0)
-        cms, cper = timed_steps(args.cold_steps)
+        cms, cper = timed_steps(args.cold_steps, marks=True)
         cold = {"ms_per_step": cms, "steps": args.cold_steps, "idle_before_s": 1.0,
                 "first5_ms": [round(float(x), 4) for x in cper[:5]],
                 "value": in_tris / (cms / 1e3) / 1e9}
         log(f"[bench] cold start: {cms:.4f} ms per step over {args.cold_steps} launches after 1 s idle")
 
     if args.calib_copy_mib:
-        nbytes = args.calib_copy_mib << 20
-        src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
-        del src, dst
+        calibration_copy(args.calib_copy_mib, dev)
 
     achieved = alg / (ms / 1e3) / 1e9
     traffic = read_traffic(kernel, args.workload)
@@ -562,7 +669,7 @@ def main():
     serving = None
     work_items = pool.work_items
     if args.workload == "batched" and not args.no_serve:
-        del graph, step, pool
+        del graph, graph_step, step, pool
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         sargs = argparse.Namespace(**vars(args))
@@ -577,13 +684,17 @@ def main():
 
     if args.workload == "batched":
         workload = (f"batched: {len(encs)} meshes (grid or sphere patch), 1e3-2e6 triangles each "
-                    "log-uniform, caps mixed 32v/64t 64v/126t 128v/256t, one persistent graph launch")
+                    "log-uniform, caps mixed 32v/64t 64v/126t 128v/256t, one batched launch per step")
+    elif args.workload == "gts":
+        workload = (f"gts: the batched workload's {len(encs)} meshes as plain GTS streams (one index byte per "
+                    "strip triangle), one batched launch per step")
     else:
-        workload = ("single mesh: icosphere level 9, caps 64v/126t, one plain launch; its streams and output fit "
-                    "the 256 MB last-level cache")
+        workload = (f"stress: {len(encs)} Delaunay triangulations of random points, 5e4-1e6 triangles each "
+                    "log-uniform, caps 64v/126t, one batched launch per step")
     out = {
         "metric": "decoded triangles/s (Gtps) + HBM GB/s, batched vs per-mesh",
         "value": in_tris / (ms / 1e3) / 1e9,
+        "format": "gts" if args.workload == "gts" else "gts-reuse",
         "unit": "Gtps",
         "n_gpus": 1,
         "steps": args.steps,
@@ -601,6 +712,7 @@ def main():
                    "prep_seconds": round(prep_s, 2)},
         "roofline": roof,
         "step_ms": step_pct,
+        "graph_replay_ms_per_step": graph_ms,
         "per_mesh": per_mesh,
         "cold_start": cold,
         "strip_triangles_per_s": strip_tris / (ms / 1e3),

@@ -18,11 +18,12 @@
 // between shapes, and all rounds of a stage are enqueued before the host
 // waits for the first (one synchronisation per stage).  A shape's
 // sample is its event interval over those launches; its figure is the
-// median over rounds.  The fastest few shapes of that first stage are then
-// measured again, alone, over three times as many rounds, and among the
-// finalists the earliest in the candidate order within kTieFraction of the
-// fastest median wins, so that shapes the measurement cannot tell apart do
-// not make the choice flip from run to run.  Every candidate decodes the
+// median over rounds.  The fastest shapes of that first stage (at least
+// kMinFinalists, and every other one within kFinalBand of the fastest, up to
+// kMaxFinalists) are then measured again, alone, over three times as many
+// rounds, and among the finalists the earliest in the candidate order within
+// kTieFraction of the fastest median wins, so that shapes the measurement
+// cannot tell apart do not make the choice flip from run to run.  Every candidate decodes the
 // whole table into its outputs, so the outputs hold the decoded meshes
 // afterwards, exactly as after one batched decode.
 #include <hip/hip_runtime_api.h>
@@ -51,7 +52,9 @@ const gtsr_launch_cfg kDefaultCfgs[] = {
     {1, 0, 32, 0, 1},     {1, 0, 32, 0, 2},     {1, 0, 32, 0, 4},
 };
 constexpr uint32_t kLaunchesPerSample = 4;
-constexpr uint32_t kFinalists = 4;
+constexpr uint32_t kMinFinalists = 4;
+constexpr uint32_t kMaxFinalists = 8;
+constexpr float kFinalBand = 0.02f;       // stage-1 medians this close to the fastest go to stage 2
 constexpr float kTieFraction = 0.01f;
 constexpr float kWarmMs = 60.0f;          // device time of back-to-back launches before measuring
 constexpr uint32_t kMaxWarmLaunches = 400;
@@ -188,11 +191,18 @@ extern "C" int gtsr_autotune_batched(const gtsr_mesh_entry* dev_mesh_table, uint
   for (uint32_t k = 0; k < n_cand; ++k) all[k] = k;
   if (int rc = stage(all, reps, warm)) return rc;
 
-  // Stage 2: the fastest few again, alone, three times as many rounds (a few
-  // launches in front cover the host's turnaround after stage 1).
+  // Stage 2: the fastest again, alone, three times as many rounds (a few
+  // launches in front cover the host's turnaround after stage 1).  A shape
+  // within the band of the fastest goes on even when it ranks below the
+  // minimum count, so that stage-1 noise among near-equal shapes does not
+  // decide which of them can win.
   std::vector<uint32_t> rank = all;
   std::stable_sort(rank.begin(), rank.end(), [&](uint32_t a, uint32_t b) { return cand[a].median < cand[b].median; });
-  std::vector<uint32_t> fin(rank.begin(), rank.begin() + std::min<uint32_t>(kFinalists, n_cand));
+  uint32_t n_fin = std::min<uint32_t>(kMinFinalists, n_cand);
+  while (n_fin < std::min<uint32_t>(kMaxFinalists, n_cand) &&
+         cand[rank[n_fin]].median <= cand[rank[0]].median * (1.0f + kFinalBand))
+    ++n_fin;
+  std::vector<uint32_t> fin(rank.begin(), rank.begin() + n_fin);
   std::sort(fin.begin(), fin.end());
   if (fin.size() > 1) {
     for (uint32_t f : fin) cand[f].samples.clear();
