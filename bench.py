@@ -536,7 +536,9 @@ def main():
         tuned = {"target_tris": best["target_tris"], "waves_per_group": best["waves_per_group"],
                  "groups_per_cu": best["groups_per_cu"], "run_tris": best["run_tris"],
                  "items_per_claim": best["items_per_claim"], "points": len(points),
-                 "median_ms": round(best["median_ms"], 4), "seconds": round(time.perf_counter() - t0, 2)}
+                 "median_ms": round(best["median_ms"], 4), "seconds": round(time.perf_counter() - t0, 2),
+                 "finalists": [[p["target_tris"], p["waves_per_group"], p["groups_per_cu"], p["run_tris"],
+                                p["items_per_claim"], round(p["median_ms"], 4)] for p in points if p["stage"] == 2]}
         log(f"[bench] autotune: {len(points)} shapes, best {best}")
     # A step is one launch of the boundary call decode_meshlets_batched over
     # the whole table.  The tuner keeps the device busy with back-to-back

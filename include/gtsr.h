@@ -422,7 +422,7 @@ typedef struct gtsr_tune_point {
  * candidates and no host wait inside a stage, so the device never idles
  * while measuring; a candidate's figure is the median over rounds of its
  * per-launch time.  The finalists -- the 4 fastest, and any others within
- * 2 % of the fastest, at most 8 in all -- are measured again alone over
+ * 1.5 % of the fastest, at most 16 in all -- are measured again alone over
  * 3 * reps rounds; among them the first in candidate order (list-major) whose
  * median is within 1 % of the fastest is *best (target_tris holds its list
  * index).

@@ -53,8 +53,8 @@ const gtsr_launch_cfg kDefaultCfgs[] = {
 };
 constexpr uint32_t kLaunchesPerSample = 4;
 constexpr uint32_t kMinFinalists = 4;
-constexpr uint32_t kMaxFinalists = 8;
-constexpr float kFinalBand = 0.02f;       // stage-1 medians this close to the fastest go to stage 2
+constexpr uint32_t kMaxFinalists = 16;
+constexpr float kFinalBand = 0.015f;      // stage-1 medians this close to the fastest go to stage 2
 constexpr float kTieFraction = 0.01f;
 constexpr float kWarmMs = 60.0f;          // device time of back-to-back launches before measuring
 constexpr uint32_t kMaxWarmLaunches = 400;
