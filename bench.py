@@ -155,6 +155,8 @@ def run_single(args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     extra = {}
+    if args.sweep:
+        extra["shapes"] = sweep_single(args, enc, dss, outs, sets, alg, stream, dev)
     if args.workload == "grid":
         lat = []
         for _ in range(50):
@@ -186,6 +188,64 @@ def run_single(args):
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": alg},
             "us_per_step": ms * 1e3, **extra}
+
+
+SWEEP_PLAIN = [(4, 8, 8), (4, 6, 8), (4, 8, 16), (8, 8, 4), (1, 8, 32), (4, 12, 8), (4, 16, 8), (4, 32, 8),
+               (1, 4, 64), (1, 2, 128), (1, 1, 256)]
+SWEEP_BATCHED = [384, 768, 1536]
+
+
+def sweep_single(args, enc, dss, outs, sets, alg, stream, dev):
+    """Launch shapes for the single-mesh step: the plain decoder over
+    (waves per group, meshlets per wave, groups per CU), and the batched
+    decoder over a one-mesh table at a few work-item sizes (one-wave groups,
+    32 per CU); 200 back-to-back launches per shape over the rotated copies,
+    median of 3 alternated rounds, every output checked against the first."""
+    import torch
+    import paper_2404_06359_amd as P
+
+    ref = P.decode(dss[0], stream=stream).clone()
+    pools = [P.Pool([enc], device=dev) for _ in range(sets)]
+    variants = [("plain", c) for c in SWEEP_PLAIN] + [("batched", t) for t in SWEEP_BATCHED]
+    times = {v: [] for v in variants}
+    for _ in range(3):
+        for v in variants:
+            k = [0]
+            if v[0] == "plain":
+                cfg = {"waves_per_group": v[1][0], "meshlets_per_wave": v[1][1], "groups_per_cu": v[1][2]}
+
+                def one():
+                    i = k[0] % sets
+                    P.decode(dss[i], out=outs[i], stream=stream, cfg=cfg)
+                    k[0] += 1
+            else:
+                for p in pools:
+                    p.plan(v[1])
+                shape = {"waves_per_group": 1, "groups_per_cu": 32}
+
+                def one():
+                    pools[k[0] % sets].decode_batched(stream, shape)
+                    k[0] += 1
+            for _ in range(2 * sets):
+                one()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(200):
+                one()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times[v].append(e0.elapsed_time(e1) / 200 * 1e3)
+            got = outs[(k[0] - 1) % sets] if v[0] == "plain" else pools[(k[0] - 1) % sets].output(0)
+            assert torch.equal(got.reshape(-1), ref.reshape(-1)), v
+    res = []
+    for v in variants:
+        us = float(np.median(times[v]))
+        res.append({"decoder": v[0], "shape": list(v[1]) if v[0] == "plain" else {"target_tris": v[1]},
+                    "us": round(us, 2), "GBps": round(alg / (us * 1e-6) / 1e9, 1)})
+        log(f"[bench] shape {v[0]} {v[1]}: {us:.2f} us")
+    del pools
+    return res
 
 
 def build_serve_prototypes(threads: int):
@@ -474,6 +534,8 @@ def main():
                     help="batched: launches that keep the device busy after tuning and while the graph is captured")
     ap.add_argument("--cold-steps", type=int, default=20,
                     help="batched: launches timed after one idle second (0 = skip)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="grid/sphere: also time a list of launch shapes (plain and batched decoders)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (a known-size "
                          "kernel for scaling hardware traffic counters)")
