@@ -531,7 +531,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="batched: skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=6000, help="batched: requests of the serving leg")
     ap.add_argument("--bridge", type=int, default=30,
-                    help="batched: launches that keep the device busy after tuning and while the graph is captured")
+                    help="batched: direct launches that keep the device busy while the graph is captured")
     ap.add_argument("--cold-steps", type=int, default=20,
                     help="batched: launches timed after one idle second (0 = skip)")
     ap.add_argument("--sweep", action="store_true",
@@ -602,20 +602,21 @@ def main():
                  "finalists": [[p["target_tris"], p["waves_per_group"], p["groups_per_cu"], p["run_tris"],
                                 p["items_per_claim"], round(p["median_ms"], 4)] for p in points if p["stage"] == 2]}
         log(f"[bench] autotune: {len(points)} shapes, best {best}")
-    # A step is one launch of the boundary call decode_meshlets_batched over
-    # the whole table.  The tuner keeps the device busy with back-to-back
-    # launches and leaves the winning work list in the pool (no re-planning),
-    # so the warm-up and timed launches continue its sustained load; the
-    # device lowers its clock for tens of milliseconds whenever sustained
-    # load starts from idle (the cold_start entry times that case).
-    step = lambda: pool.decode_batched(stream, cfg)
+    # A step is one replay of a captured graph holding one launch of the
+    # boundary call decode_meshlets_batched over the whole table.  The tuner
+    # keeps the device busy with back-to-back launches and leaves the winning
+    # work list in the pool (no re-planning).  Right after it, direct launches
+    # of the same call are enqueued so that the device stays busy while the
+    # host captures the graph: the device slows down for about ten
+    # milliseconds a few milliseconds after any idle stretch (the cold_start
+    # entry times the case from an idle second), and these launches absorb
+    # that before the warm-up and timed replays.
+    direct = lambda: pool.decode_batched(stream, cfg)
     kernel = "decode_gts_batched" if args.workload == "gts" else "decode_batched"
-    # The host's work between the tuner's last launch and the first warm-up
-    # launch idles the device for a moment, and the device slows down for
-    # about ten milliseconds a few milliseconds after that; launches enqueued
-    # right away cover it (1 % faster timed steps, measured).
     for _ in range(args.bridge):
-        step()
+        direct()
+    graph = pool.batched_graph(cfg)
+    step = lambda: graph(stream)
 
     def timed_steps(n, fn=None, marks=False):
         """n steps between two events (no host wait in between); with marks,
@@ -642,17 +643,10 @@ def main():
     # the same steps again, each followed by an event, for per-step percentiles
     _, per_step = timed_steps(args.steps, marks=True)
     step_pct = {f"p{q}": round(float(np.percentile(per_step, q)), 4) for q in (10, 50, 90)}
-    # and as replays of a captured graph holding the same launch; direct
-    # launches keep the device busy while the host captures it
-    for _ in range(args.bridge):
-        step()
-    graph = pool.batched_graph(cfg)
-    graph_step = lambda: graph(stream)
-    for _ in range(args.warmup):
-        graph_step()
-    graph_ms, _ = timed_steps(args.steps, fn=graph_step)
-    log(f"[bench] {kernel}: {ms:.4f} ms per step (direct launches), per-step {step_pct}; "
-        f"graph replays {graph_ms:.4f} ms")
+    # and as direct launches of the same call (no graph)
+    direct_ms, _ = timed_steps(args.steps, fn=direct)
+    log(f"[bench] {kernel}: {ms:.4f} ms per step (graph replays), per-step {step_pct}; "
+        f"direct launches {direct_ms:.4f} ms")
 
     # Achievable bandwidth for this traffic mix: the calibration kernel reads
     # and writes the decode's algorithmic byte counts with its access pattern.
@@ -733,7 +727,7 @@ def main():
     serving = None
     work_items = pool.work_items
     if args.workload == "batched" and not args.no_serve:
-        del graph, graph_step, step, pool
+        del graph, direct, step, pool
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         sargs = argparse.Namespace(**vars(args))
@@ -748,13 +742,13 @@ def main():
 
     if args.workload == "batched":
         workload = (f"batched: {len(encs)} meshes (grid or sphere patch), 1e3-2e6 triangles each "
-                    "log-uniform, caps mixed 32v/64t 64v/126t 128v/256t, one batched launch per step")
+                    "log-uniform, caps mixed 32v/64t 64v/126t 128v/256t, one graph-captured batched launch per step")
     elif args.workload == "gts":
         workload = (f"gts: the batched workload's {len(encs)} meshes as plain GTS streams (one index byte per "
-                    "strip triangle), one batched launch per step")
+                    "strip triangle), one graph-captured batched launch per step")
     else:
         workload = (f"stress: {len(encs)} Delaunay triangulations of random points, 5e4-1e6 triangles each "
-                    "log-uniform, caps 64v/126t, one batched launch per step")
+                    "log-uniform, caps 64v/126t, one graph-captured batched launch per step")
     out = {
         "metric": "decoded triangles/s (Gtps) + HBM GB/s, batched vs per-mesh",
         "value": in_tris / (ms / 1e3) / 1e9,
@@ -776,7 +770,7 @@ def main():
                    "prep_seconds": round(prep_s, 2)},
         "roofline": roof,
         "step_ms": step_pct,
-        "graph_replay_ms_per_step": graph_ms,
+        "direct_launch_ms_per_step": direct_ms,
         "per_mesh": per_mesh,
         "cold_start": cold,
         "strip_triangles_per_s": strip_tris / (ms / 1e3),
