@@ -4,9 +4,17 @@
 Default workload (one step = one decode of all of it): 2000 synthetic meshes
 (regular grids and sphere patches, triangle counts log-uniform in [1e3, 2e6],
 meshlet caps drawn from 32v/64t, 64v/126t, 128v/256t), encoded on the host,
-resident in HBM, decoded by one HIP-graph launch.  Beside it: the
-same meshes decoded with one plain launch per mesh, and the oracle's
-sequential decoder timed on the host cores.
+resident in HBM, decoded by one replay of a captured graph holding one
+batched launch (autotuned launch shape).  Beside it: the same launch issued
+directly, the same meshes decoded with one plain launch per mesh, the first
+launches after an idle second, a copy kernel with the decode's access pattern
+(the achievable bandwidth), the oracle's sequential decoder timed on the host
+cores, and a short serving run (p50/p99 request latency).
+
+Other workloads (``--workload``): gts (the same meshes as plain GTS
+streams), stress (Delaunay meshes), grid and sphere (one plain launch per
+mesh), compact, cull and dequant (the next-row features on the sphere), and
+serve (the decode server under a Poisson request stream).
 
 Prints one JSON line (rank 0).  ``--gpus`` above 1 is refused: the decode has
 no cross-GPU step and this benchmark drives a single device.
