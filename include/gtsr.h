@@ -53,7 +53,8 @@ enum {
   GTSR_ECORRUPT = -5,     /* gtsr_validate found a violated stream invariant */
   GTSR_EHIP = -6,         /* a HIP runtime call failed */
   GTSR_ECANCELED = -7,    /* serving: the request was withdrawn before admission */
-  GTSR_EBUSY = -8         /* serving: too late to withdraw, the request was already admitted */
+  GTSR_EBUSY = -8,        /* serving: too late to withdraw, the request was already admitted */
+  GTSR_EIO = -9           /* a file could not be opened, read or written */
 };
 
 /* Stream formats (Sec. 4.2 / 4.3; Fig. "Strip Encoding" (c) and (d)). */
@@ -535,6 +536,57 @@ int gtsr_server_replay(gtsr_server* server, const uint64_t* arrival_ns, const ui
 /* Stop the scheduler, wait for batches on the device, free everything the
  * server allocated (not the arena). */
 void gtsr_server_destroy(gtsr_server* server);
+
+/* ------------------------------------------------------- .gtsr files */
+
+/* A versioned container of encoded meshes, so that a pool is encoded once,
+ * offline, and reloaded for decoding (the paper encodes in the asset
+ * pipeline and decodes at run time, Sec. 1).  Layout (little-endian): a
+ * 64-byte header (magic "GTSRFILE", version 1, mesh count, table and data
+ * offsets, total size, 64-bit FNV-1a hash of everything after the header), a
+ * 128-byte record per mesh (format, counts, sizes, the offset of each
+ * array), then the arrays, each on a 16-byte boundary. */
+typedef struct gtsr_file gtsr_file;   /* opaque: an opened, checked file in host memory */
+
+/* One mesh as written to or read from a file: the encoder's host arrays.
+ * Plain GTS (format GTSR_FORMAT_GTS) keeps its L/R words in bits and its
+ * index bytes in reuse, as gtsr_gts_from_reuse writes them. */
+typedef struct gtsr_file_mesh {
+  uint32_t format;              /* GTSR_FORMAT_REUSE or GTSR_FORMAT_GTS */
+  uint32_t meshlet_count;
+  uint64_t strip_triangles, input_triangles, restarts;
+  const gtsr_meshlet* meshlets; /* meshlet_count descriptors */
+  const uint8_t* bits;
+  uint64_t bits_bytes;
+  const uint8_t* reuse;
+  uint64_t reuse_bytes;
+  const uint32_t* vertices;     /* local -> global vertex ids, meshlet after meshlet */
+  uint64_t vertex_count;
+  const uint64_t* vert_off;     /* meshlet_count + 1 entries */
+  const uint32_t* kept_off;     /* meshlet_count + 1 entries, or NULL (not stored) */
+  const uint32_t* tri_ids;      /* input_triangles entries, or NULL (not stored) */
+} gtsr_file_mesh;
+
+/* Write mesh_count meshes to path (host arrays, read during the call only;
+ * kept_off and tri_ids may be NULL).  The file appears whole or not at all
+ * (written under path + ".partial", then renamed).  Errors: EINVAL (null
+ * argument or array, bad format), ENOMEM, EIO. */
+int gtsr_file_write(const char* path, const gtsr_file_mesh* meshes, uint32_t mesh_count);
+
+/* Read a whole file into host memory and check it: header, sizes and offsets
+ * against the file, the hash, and every mesh against its format's stream
+ * invariants (gtsr_validate for GTS-Reuse, Sec. 4.3) and its vertex and kept
+ * offsets.  *file is set only on success.  Errors: EINVAL, ENOMEM, EIO (cannot
+ * open or read), ECORRUPT (anything that does not check out). */
+int gtsr_file_open(const char* path, gtsr_file** file);
+
+int gtsr_file_mesh_count(const gtsr_file* file, uint32_t* count);
+
+/* Mesh i of an opened file; the pointers point into the file's memory and stay
+ * valid until gtsr_file_close.  Errors: EINVAL (null, index out of range). */
+int gtsr_file_mesh_get(const gtsr_file* file, uint32_t i, gtsr_file_mesh* mesh);
+
+void gtsr_file_close(gtsr_file* file);
 
 /* ------------------------------------------------- vertex attributes */
 

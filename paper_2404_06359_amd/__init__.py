@@ -19,7 +19,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 # one for CPU test runs); by default the in-tree build is loaded.
 LIB_PATH = os.environ.get("GTSR_LIBRARY") or os.path.join(PKG, "libgtsr.so")
 
-OK, EINVAL, ENOMEM, EDEGENERATE, ELIMIT, ECORRUPT, EHIP, ECANCELED, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7, -8
+OK, EINVAL, ENOMEM, EDEGENERATE, ELIMIT, ECORRUPT, EHIP, ECANCELED, EBUSY, EIO = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 FORMAT_REUSE, FORMAT_GTS = 0, 1
 
 EXPORTED = (
@@ -32,6 +32,7 @@ EXPORTED = (
     "gtsr_gts_from_reuse", "gtsr_decode_gts", "gtsr_decode_gts_batched", "gtsr_decode_compact",
     "gtsr_quantize_attributes", "gtsr_dequantize", "gtsr_min_strips", "gtsr_meshlet_cones",
     "gtsr_decode_culled", "gtsr_stream_calib", "gtsr_decode_batched_noalloc",
+    "gtsr_file_write", "gtsr_file_open", "gtsr_file_mesh_count", "gtsr_file_mesh_get", "gtsr_file_close",
 )
 
 
@@ -70,6 +71,14 @@ class StreamDesc(C.Structure):
                 ("meshlet_count", C.c_uint32), ("reserved", C.c_uint32),
                 ("bits_bytes", C.c_uint64), ("reuse_bytes", C.c_uint64),
                 ("strip_triangles", C.c_uint64)]
+
+
+class FileMesh(C.Structure):
+    _fields_ = [("format", C.c_uint32), ("meshlet_count", C.c_uint32), ("strip_triangles", C.c_uint64),
+                ("input_triangles", C.c_uint64), ("restarts", C.c_uint64), ("meshlets", C.c_void_p),
+                ("bits", C.c_void_p), ("bits_bytes", C.c_uint64), ("reuse", C.c_void_p),
+                ("reuse_bytes", C.c_uint64), ("vertices", C.c_void_p), ("vertex_count", C.c_uint64),
+                ("vert_off", C.c_void_p), ("kept_off", C.c_void_p), ("tri_ids", C.c_void_p)]
 
 
 class LaunchCfg(C.Structure):
@@ -174,6 +183,11 @@ def lib():
                                          C.POINTER(LaunchCfg), vp]),
         "gtsr_stream_calib": (C.c_int, [vp, u64, vp, u64, C.POINTER(LaunchCfg), C.POINTER(u64), vp]),
         "gtsr_decode_batched_noalloc": (C.c_int, [vp, u32, vp, u32, u32, C.POINTER(LaunchCfg), vp]),
+        "gtsr_file_write": (C.c_int, [C.c_char_p, vp, u32]),
+        "gtsr_file_open": (C.c_int, [C.c_char_p, C.POINTER(vp)]),
+        "gtsr_file_mesh_count": (C.c_int, [vp, C.POINTER(u32)]),
+        "gtsr_file_mesh_get": (C.c_int, [vp, u32, C.POINTER(FileMesh)]),
+        "gtsr_file_close": (None, [vp]),
     }
     for name, (rt, args) in sig.items():
         f = getattr(L, name)
@@ -271,6 +285,62 @@ def encode(tri: np.ndarray, nverts: int, max_vertices: int = 64, max_triangles: 
     finally:
         L.gtsr_encoded_free(h)
     return Encoded(meshlets, bits, reuse, verts, vert_off, stats, kept_off, tri_ids)
+
+
+def _take(ptr, n, dt):
+    """A numpy copy of n elements of dtype dt at a host address."""
+    if n == 0 or not ptr:
+        return np.zeros(0, dt)
+    buf = (C.c_uint8 * (n * np.dtype(dt).itemsize)).from_address(ptr)
+    return np.frombuffer(buf, dtype=dt, count=n).copy()
+
+
+def save(path: str, encs) -> None:
+    """Write encoded meshes (``Encoded``, either format) to a ``.gtsr`` file
+    (``gtsr_file_write``)."""
+    n = len(encs)
+    arr = (FileMesh * max(n, 1))()
+    keep = []
+    ptr = lambda a: a.ctypes.data if a is not None and a.size else None
+    for i, e in enumerate(encs):
+        parts = [np.ascontiguousarray(x) for x in (e.meshlets, e.bits, e.reuse, e.verts, e.vert_off)]
+        kept = None if e.kept_off is None or not e.kept_off.size else np.ascontiguousarray(e.kept_off, np.uint32)
+        tids = None if e.tri_ids is None or not e.tri_ids.size else np.ascontiguousarray(e.tri_ids, np.uint32)
+        keep.append((parts, kept, tids))
+        arr[i] = FileMesh(e.format, e.meshlet_count, e.strip_triangles, int(e.stats.get("input_triangles", 0)),
+                          int(e.stats.get("restarts", 0)), ptr(parts[0]), ptr(parts[1]), parts[1].nbytes,
+                          ptr(parts[2]), parts[2].nbytes, ptr(parts[3]), parts[3].size, ptr(parts[4]),
+                          ptr(kept), ptr(tids))
+    _check(lib().gtsr_file_write(os.fsencode(path), arr, n))
+
+
+def load(path: str) -> list:
+    """Read and check a ``.gtsr`` file (``gtsr_file_open``); returns its meshes
+    as ``Encoded`` (numpy copies; the file's memory is released)."""
+    L = lib()
+    h = C.c_void_p()
+    _check(L.gtsr_file_open(os.fsencode(path), C.byref(h)))
+    try:
+        cnt = C.c_uint32()
+        _check(L.gtsr_file_mesh_count(h, C.byref(cnt)))
+        out = []
+        for i in range(cnt.value):
+            g = FileMesh()
+            _check(L.gtsr_file_mesh_get(h, i, C.byref(g)))
+            M = g.meshlet_count
+            stats = {"input_triangles": int(g.input_triangles), "strip_triangles": int(g.strip_triangles),
+                     "restarts": int(g.restarts)}
+            if g.format == FORMAT_REUSE:
+                stats["reuse_count"] = int(g.reuse_bytes)
+            out.append(Encoded(_take(g.meshlets, M, MESHLET_DTYPE), _take(g.bits, g.bits_bytes, np.uint8),
+                               _take(g.reuse, g.reuse_bytes, np.uint8), _take(g.vertices, g.vertex_count, np.uint32),
+                               _take(g.vert_off, M + 1, np.uint64), stats,
+                               _take(g.kept_off, M + 1, np.uint32) if g.kept_off else None,
+                               _take(g.tri_ids, g.input_triangles, np.uint32) if g.tri_ids else None,
+                               int(g.format)))
+        return out
+    finally:
+        L.gtsr_file_close(h)
 
 
 def min_strips(tri: np.ndarray, node_limit: int = 1_000_000):

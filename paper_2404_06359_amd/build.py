@@ -21,7 +21,7 @@ ARCH = os.environ.get("GTSR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")
 
-HOST_SOURCES = ["encode.cpp", "capi.cpp", "tune.cpp", "serve.cpp", "quant.cpp", "cones.cpp"]
+HOST_SOURCES = ["encode.cpp", "capi.cpp", "tune.cpp", "serve.cpp", "quant.cpp", "cones.cpp", "gtsrfile.cpp"]
 HIP_SOURCES = ["decode.hip", "attrs.hip", "calib.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]
@@ -69,7 +69,7 @@ SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "
 def build_sanitized(verbose: bool = False) -> str:
     """A host-sanitized copy of the library for CPU test runs:
     ``_build/sanitize/libgtsr.so``.  The host C++ (encoder, validator,
-    planner, quantizer, cones, tuner, server) is compiled by g++ with
+    planner, quantizer, cones, tuner, server, .gtsr files) is compiled by g++ with
     AddressSanitizer and UndefinedBehaviorSanitizer; the HIP translation
     units keep their normal build (no sanitizer reaches device code).  Load
     it by setting GTSR_LIBRARY to its path, with the sanitizer runtime

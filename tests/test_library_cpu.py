@@ -57,7 +57,7 @@ def test_struct_layouts_match_header(tmp_path):
         "gtsr_stream": P.StreamDesc, "gtsr_launch_cfg": P.LaunchCfg, "gtsr_tune_point": P.TunePoint,
         "gtsr_server_params": P.ServerParams, "gtsr_server_stats": P.ServerStats,
         "gtsr_mesh_entry": P.MESH_ENTRY_DTYPE, "gtsr_work_item": P.WORK_ITEM_DTYPE,
-        "gtsr_completion": P.COMPLETION_DTYPE, "gtsr_attr_stream": P.AttrStream,
+        "gtsr_completion": P.COMPLETION_DTYPE, "gtsr_attr_stream": P.AttrStream, "gtsr_file_mesh": P.FileMesh,
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gtsr.h"', "int main(void) {"]
     want = []
