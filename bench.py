@@ -602,7 +602,7 @@ def main():
         # leaves the winning work list in the pool: no re-planning, so the
         # timed launches follow the tuner's with no idle device between
         t0 = time.perf_counter()
-        cfg, best, points = pool.autotune(stream=stream)
+        cfg, best, points = pool.autotune(stream=stream, mode="search", cache=None)
         tuned = {"target_tris": best["target_tris"], "waves_per_group": best["waves_per_group"],
                  "groups_per_cu": best["groups_per_cu"], "run_tris": best["run_tris"],
                  "items_per_claim": best["items_per_claim"], "points": len(points),

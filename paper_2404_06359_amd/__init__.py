@@ -287,6 +287,52 @@ def encode(tri: np.ndarray, nverts: int, max_vertices: int = 64, max_triangles: 
     return Encoded(meshlets, bits, reuse, verts, vert_off, stats, kept_off, tri_ids)
 
 
+def tune_key(arch: str, cus: int, fmt: int, meshes: int, strip_tris: int, meshlets: int) -> str:
+    """Autotune cache key: the device and the workload's size class (mesh
+    count and strip-triangle total to the nearest power of two, strip
+    triangles per meshlet to the nearest multiple of 8)."""
+    import math
+
+    lg = lambda x: int(round(math.log2(x))) if x > 0 else -1
+    per = int(round(strip_tris / meshlets / 8.0)) * 8 if meshlets else 0
+    return f"{arch}/cu{cus}/{'gts' if fmt == FORMAT_GTS else 'reuse'}/m2^{lg(meshes)}/t2^{lg(strip_tris)}/tpm{per}"
+
+
+def tune_cache_get(path: str, key: str):
+    """The recorded pick for key in a JSON autotune cache, or None (also when
+    the file is missing or unreadable)."""
+    import json
+
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        rec = data.get("entries", {}).get(key)
+    except (OSError, ValueError, AttributeError):
+        return None
+    if not isinstance(rec, dict) or not {"target_tris", "cfg", "best"} <= rec.keys():
+        return None
+    return rec
+
+
+def tune_cache_put(path: str, key: str, rec: dict) -> None:
+    """Record a pick under key (the file is rewritten whole, by rename)."""
+    import json
+
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        if not isinstance(data, dict) or not isinstance(data.get("entries"), dict):
+            data = {}
+    except (OSError, ValueError):
+        data = {}
+    data.setdefault("version", 1)
+    data.setdefault("entries", {})[key] = rec
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 def _take(ptr, n, dt):
     """A numpy copy of n elements of dtype dt at a host address."""
     if n == 0 or not ptr:
@@ -700,14 +746,51 @@ class Pool:
 
     TUNE_TARGETS = (384, 768, 1536, 3072)
 
-    def autotune(self, targets=None, cfgs=None, reps: int = 5, stream=None):
+    def tune_key(self) -> str:
+        """The autotune cache key of this pool: device (architecture, CU
+        count), stream format, and the workload's size class (meshes,
+        strip triangles, strip triangles per meshlet, each rounded to a
+        power-of-two or 8-triangle bucket)."""
+        torch = _torch()
+        props = torch.cuda.get_device_properties(self.table.device)
+        return tune_key(getattr(props, "gcnArchName", props.name), props.multi_processor_count, self.format,
+                        self.mesh_count, int(self.strip_tris.sum()), int(self.meshlet_counts.sum()))
+
+    def autotune(self, targets=None, cfgs=None, reps: int = 5, stream=None, mode=None, cache=None):
         """Measure the batched decoder over work-list targets x launch shapes
         (``gtsr_autotune_batched``) and keep the fastest: the pool's work list
         becomes the winning one (planned and uploaded before measuring, so no
         host work separates tuning from use).  Returns ``(best_cfg, best,
         points)``: ``best_cfg`` is a dict for ``decode_batched`` /
         ``batched_graph``; ``best`` and ``points`` are ``TunePoint.as_dict()``
-        records whose ``target_tris`` is the target (not the list index)."""
+        records whose ``target_tris`` is the target (not the list index).
+
+        ``mode`` (default: the ``GTSR_AUTOTUNE`` environment variable, else
+        "search"): "search" always measures and records the pick in the
+        cache file, if one is named; "cache" takes the pick recorded for this
+        pool's ``tune_key()`` without measuring (``points`` is then empty)
+        and measures only when there is none; "off" measures nothing and
+        plans the default work list with the default shape.  ``cache``: a
+        JSON file (default: ``GTSR_AUTOTUNE_CACHE``)."""
+        mode = mode or os.environ.get("GTSR_AUTOTUNE", "search")
+        cache = cache or os.environ.get("GTSR_AUTOTUNE_CACHE")
+        if mode not in ("search", "cache", "off"):
+            raise ValueError(f"autotune mode must be search, cache or off, not {mode!r}")
+        if mode == "off":
+            self.plan()
+            return {"waves_per_group": 0, "groups_per_cu": 0, "run_tris": 0, "items_per_claim": 0}, None, []
+        key = self.tune_key() if cache else None
+        if mode == "cache" and cache:
+            hit = tune_cache_get(cache, key)
+            if hit is not None:
+                self.plan(hit["target_tris"])
+                return dict(hit["cfg"]), dict(hit["best"]), []
+        cfg, best, points = self._measure(targets, cfgs, reps, stream)
+        if cache:
+            tune_cache_put(cache, key, {"target_tris": best["target_tris"], "cfg": cfg, "best": best})
+        return cfg, best, points
+
+    def _measure(self, targets, cfgs, reps, stream):
         torch = _torch()
         L = lib()
         tg = [int(t) for t in (targets or self.TUNE_TARGETS)]

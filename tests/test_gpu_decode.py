@@ -287,6 +287,44 @@ def test_batched_graph_replays():
     g.close()
 
 
+def test_autotune_cache_modes(tmp_path):
+    """mode "search" measures and records the pick under the pool's key;
+    "cache" then takes it without measuring and plans the same work list;
+    "off" measures nothing.  Every mode leaves a work list that decodes every
+    mesh to the oracle's bytes."""
+    encs = [O.encode(m.tri, m.nverts, *caps) for m, caps in _batched_meshes()]
+    refs = [O.decode(s) for s in encs]
+    libencs = [P.encode(m.tri, m.nverts, *caps) for m, caps in _batched_meshes()]
+    pool = P.Pool(libencs)
+    cache = str(tmp_path / "tune.json")
+    cfgs = [{"waves_per_group": 1, "groups_per_cu": 8, "run_tris": 1280}, {"waves_per_group": 2, "groups_per_cu": 4}]
+    say("[gpu] autotune search with a cache file")
+    cfg, best, points = pool.autotune(targets=[300, 2000], cfgs=cfgs, reps=2, mode="search", cache=cache)
+    assert len(points) == 4
+    items = pool.work_items
+    hit = P.tune_cache_get(cache, pool.tune_key())
+    assert hit is not None and hit["target_tris"] == best["target_tris"] and hit["cfg"] == cfg
+
+    def check(c):
+        pool.out.fill_(0x55)
+        pool.decode_batched(cfg=c)
+        torch.cuda.synchronize()
+        for i, ref in enumerate(refs):
+            np.testing.assert_array_equal(pool.output(i).cpu().numpy(), ref)
+
+    check(cfg)
+    pool.plan(768)                      # something else in between
+    say("[gpu] autotune from the cache")
+    cfg2, best2, points2 = pool.autotune(mode="cache", cache=cache)
+    assert points2 == [] and cfg2 == cfg and best2["target_tris"] == best["target_tris"]
+    assert pool.work_items == items
+    check(cfg2)
+    say("[gpu] autotune off")
+    cfg3, best3, points3 = pool.autotune(mode="off")
+    assert best3 is None and points3 == [] and not any(cfg3.values())
+    check(cfg3)
+
+
 def test_autotune_picks_a_measured_shape_and_keeps_outputs():
     encs = [O.encode(m.tri, m.nverts, *caps) for m, caps in _batched_meshes()]
     refs = [O.decode(s) for s in encs]
