@@ -4,6 +4,7 @@
   decoded by one graph launch in the shape the benchmark times (autotuned),
   by the untuned default launch and by one plain launch per mesh; every
   output byte equals the oracle's decode of the same stream.
+* The same meshes as plain GTS streams, tuned and replayed from a graph.
 * The serving pool (5000 meshes, 12.8G triangles, 13.8 GB of streams) under
   the 64 GB budget with the benchmark's server settings: a burst of requests
   decoded together equals the oracle, and a sample of them equals its own
@@ -91,6 +92,26 @@ def test_batched_workload_full_size(batched):
     pool.out.fill_(0x55)
     pool.decode_per_mesh()
     assert_pool_output(pool, refs, "per-mesh launches")
+
+
+@pytest.mark.timeout(900)
+def test_plain_gts_batched_full_size(batched):
+    """The same 2000 meshes as plain GTS streams (library conversion), tuned
+    and replayed from a captured graph: every triple equals the oracle's
+    decode of the original GTS-Reuse stream (same strips, same flags)."""
+    encs, refs = batched
+    say("[gpu] full size: plain GTS conversion of the batched workload")
+    gts = [P.gts_from_reuse(e) for e in encs]
+    pool = P.Pool(gts)
+    assert pool.format == P.FORMAT_GTS
+    cfg, best, points = pool.autotune(mode="search", cache=None)
+    say(f"[gpu] full size: plain GTS autotuned over {len(points)} shapes: {best}")
+    g = pool.batched_graph(cfg)
+    for fill in (0xAA, 0x55):
+        pool.out.fill_(fill)
+        g()
+        assert_pool_output(pool, refs, f"plain GTS graph replay (fill {fill:#x})")
+    g.close()
 
 
 @pytest.mark.timeout(900)
