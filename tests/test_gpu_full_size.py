@@ -2,7 +2,8 @@
 
 * The batched workload (2000 meshes, 526M input triangles, mixed caps):
   decoded by one graph launch in the shape the benchmark times (autotuned),
-  by the untuned default launch and by one plain launch per mesh; every
+  by the untuned default launch, by a persistent claiming launch and by one
+  plain launch per mesh; every
   output byte equals the oracle's decode of the same stream.
 * The same meshes as plain GTS streams, tuned and replayed from a graph.
 * The serving pool (5000 meshes, 12.8G triangles, 13.8 GB of streams) under
@@ -88,6 +89,10 @@ def test_batched_workload_full_size(batched):
     pool.out.fill_(0xAA)
     pool.decode_batched()
     assert_pool_output(pool, refs, "default batched launch")
+    say("[gpu] full size: persistent grid claiming 4 items at a time")
+    pool.out.fill_(0x55)
+    pool.decode_batched(cfg={"waves_per_group": 1, "groups_per_cu": 32, "items_per_claim": 4})
+    assert_pool_output(pool, refs, "claiming launch")
     say("[gpu] full size: one plain launch per mesh")
     pool.out.fill_(0x55)
     pool.decode_per_mesh()
