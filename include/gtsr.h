@@ -293,9 +293,12 @@ int gtsr_decode_compact(const gtsr_stream* dev, uint32_t format, const uint32_t*
  * the input triangles tri_ids[kept_off[m] .. kept_off[m+1]) of indices
  * (gtsr_encoded_view), vertex positions float32[vertex_count][3].  Writes
  * cones float32[meshlet_count][4] = {axis x, y, z, cutoff}: axis = the
- * normalised sum of the unit triangle normals (p1-p0) x (p2-p0) (zero-area
- * triangles ignored), cutoff = sin(largest angle between axis and a normal)
- * + 1e-5, or 2 when that angle is 90 degrees or more (never culled).
+ * normalised sum, in tri_ids order, of the unit triangle normals
+ * (p1-p0) x (p2-p0), each triangle first rotated (orientation kept) to start
+ * at its smallest vertex id (zero-area triangles ignored), cutoff =
+ * sin(largest angle between axis and a normal) + 1e-5, or 2 when that angle
+ * is 90 degrees or more (never culled); float64 arithmetic, rounded once to
+ * float32, so the result depends only on the triangles and their order.
  * Errors: EINVAL. */
 int gtsr_meshlet_cones(const uint32_t* indices, uint64_t triangle_count, const float* positions,
                        uint32_t vertex_count, const uint32_t* tri_ids, const uint32_t* kept_off,

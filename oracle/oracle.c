@@ -445,13 +445,17 @@ int oracle_dequantize(const int32_t* L, const uint16_t* q, const uint64_t* vert_
 /*
  * Cones from decoded meshlets: the triangles of meshlet m are its decoded
  * triples (restart degenerates, which repeat a vertex, dropped) mapped through
- * its vertex list to positions float32[nverts][3].  Unit normal of (p0,p1,p2):
- * (p1-p0) x (p2-p0) normalised (zero-area triangles ignored); axis = the
- * normalised sum of the unit normals; cos_min = the smallest dot(axis, n).
- * Output per meshlet {axis x, y, z, cutoff} in float32 with cutoff =
- * sqrt(1 - cos_min^2) + 1e-5 (sin of the half-angle plus a rounding margin),
- * or 2 when cos_min <= 0 or the normals cancel (the cone is a half-space or
- * more: never culled).
+ * its vertex list to global vertex ids, in strip order.  Each triangle is
+ * rotated (orientation kept) to start at its smallest global id, and its unit
+ * normal is (p1-p0) x (p2-p0) normalised (zero-area triangles ignored), with
+ * positions float32[nverts][3] and float64 arithmetic; axis = the normalised
+ * sum of the unit normals in strip order; cos_min = the smallest
+ * dot(axis, n).  Output per meshlet {axis x, y, z, cutoff} in float32 with
+ * cutoff = sqrt(max(0, 1 - cos_min^2)) + 1e-5 (sin of the half-angle plus a
+ * rounding margin), or 2 when cos_min <= 0 or the normals cancel (the cone
+ * is a half-space or more: never culled).  The rotation fixes the rounding of
+ * each normal, so any construction that takes the same triangles in the same
+ * order gets the same bits.
  */
 int oracle_cones(const uint8_t* desc, uint32_t meshlet_count, const uint8_t* decoded,
                  const uint32_t* verts, const uint64_t* vert_off, const float* pos, uint32_t nverts,
@@ -466,14 +470,18 @@ int oracle_cones(const uint8_t* desc, uint32_t meshlet_count, const uint8_t* dec
     for (uint32_t t = 0; t < T; ++t) {
       const uint8_t* x = decoded + 3ull * (out_off + t);
       if (x[0] == x[1] || x[1] == x[2] || x[0] == x[2]) continue;
-      double p[3][3];
+      uint32_t g[3];
       for (int c = 0; c < 3; ++c) {
         uint64_t k = vert_off[m] + x[c];
         if (k >= vert_off[m + 1]) { free(un); return OR_ECORRUPT; }
-        uint32_t v = verts[k];
-        if (v >= nverts) { free(un); return OR_EINVAL; }
-        for (int j = 0; j < 3; ++j) p[c][j] = pos[3ull * v + j];
+        g[c] = verts[k];
+        if (g[c] >= nverts) { free(un); return OR_EINVAL; }
       }
+      /* start at the smallest id, same cyclic order */
+      int r = g[1] < g[0] ? (g[2] < g[1] ? 2 : 1) : (g[2] < g[0] ? 2 : 0);
+      double p[3][3];
+      for (int c = 0; c < 3; ++c)
+        for (int j = 0; j < 3; ++j) p[c][j] = pos[3ull * g[(c + r) % 3] + j];
       double a[3] = {p[1][0] - p[0][0], p[1][1] - p[0][1], p[1][2] - p[0][2]};
       double b[3] = {p[2][0] - p[0][0], p[2][1] - p[0][1], p[2][2] - p[0][2]};
       double n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
@@ -494,7 +502,7 @@ int oracle_cones(const uint8_t* desc, uint32_t meshlet_count, const uint8_t* dec
         if (c < cmin) cmin = c;
       }
       o[0] = (float)ax[0]; o[1] = (float)ax[1]; o[2] = (float)ax[2];
-      o[3] = cmin <= 0.0 ? 2.0f : (float)(sqrt(1.0 - cmin * cmin) + 1e-5);
+      o[3] = cmin <= 0.0 ? 2.0f : (float)(sqrt(fmax(0.0, 1.0 - cmin * cmin)) + 1e-5);
     }
     free(un);
   }

@@ -2,8 +2,11 @@
 // the amplification shader tests a cone of the meshlet's triangle normals and
 // drops meshlets that face entirely away).  Host side, offline.
 //
-// Cone of a meshlet: axis = the normalised sum of its triangles' unit
-// normals ((p1 - p0) x (p2 - p0), zero-area triangles ignored); the opening
+// Cone of a meshlet: axis = the normalised sum, in strip order, of its
+// triangles' unit normals ((p1 - p0) x (p2 - p0) in float64, each triangle
+// rotated -- orientation kept -- to start at its smallest vertex id, so that
+// every construction from the same triangles in the same order rounds the
+// same way; zero-area triangles ignored); the opening
 // half-angle theta is the largest angle between the axis and a normal.  For a
 // view direction d (unit, from the eye into the scene), a triangle with
 // normal n faces away when dot(n, d) > 0; every triangle of the cone does
@@ -33,12 +36,15 @@ extern "C" int gtsr_meshlet_cones(const uint32_t* indices, uint64_t triangle_cou
     for (uint32_t k = kept_off[m]; k < kept_off[m + 1]; ++k) {
       const uint32_t t = tri_ids[k];
       if (t >= triangle_count) return fail(GTSR_EINVAL, std::string(who) + ": triangle id out of range");
-      double p[3][3];
+      uint32_t g[3];
       for (int c = 0; c < 3; ++c) {
-        const uint32_t v = indices[3ull * t + c];
-        if (v >= vertex_count) return fail(GTSR_EINVAL, std::string(who) + ": vertex id out of range");
-        for (int j = 0; j < 3; ++j) p[c][j] = positions[3ull * v + j];
+        g[c] = indices[3ull * t + c];
+        if (g[c] >= vertex_count) return fail(GTSR_EINVAL, std::string(who) + ": vertex id out of range");
       }
+      const int r = g[1] < g[0] ? (g[2] < g[1] ? 2 : 1) : (g[2] < g[0] ? 2 : 0);   // smallest id first
+      double p[3][3];
+      for (int c = 0; c < 3; ++c)
+        for (int j = 0; j < 3; ++j) p[c][j] = positions[3ull * g[(c + r) % 3] + j];
       const double ax = p[1][0] - p[0][0], ay = p[1][1] - p[0][1], az = p[1][2] - p[0][2];
       const double bx = p[2][0] - p[0][0], by = p[2][1] - p[0][1], bz = p[2][2] - p[0][2];
       const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;

@@ -593,20 +593,24 @@ def test_stress_delaunay_full_size():
 @pytest.mark.parametrize("caps", [(32, 64), (128, 256)])
 def test_culled_decode(caps):
     """Cone culling in front of the decode: culled meshlets keep the fill
-    pattern, every other meshlet equals the oracle decode; the culled set
-    equals the oracle's decision on the same cones."""
+    pattern, every other meshlet equals the oracle decode; the culled set is
+    the oracle's decision on the oracle's own cones (built from its decoded
+    triples), which equal the library's bit for bit."""
     m = meshgen.sphere(6, meshgen.rng_for(2, 44))
     pos = meshgen.vertex_attributes(m)[:, :3].copy()
     e = P.encode(m.tri, m.nverts, *caps)
     cones = P.meshlet_cones(m.tri, pos, e)
     ref = O.decode_arrays(e.desc_bytes, e.bits, e.reuse, e.strip_triangles)
+    so = O.Stream(e.desc_bytes, e.bits, e.reuse, e.verts, e.vert_off, e.stats)
+    ocones = O.cones(so, O.decode(so), pos)
+    np.testing.assert_array_equal(cones.view(np.uint32), ocones.view(np.uint32))
     ds = P.to_device(e)
     cdev = P.upload_padded(cones.view(np.uint8).reshape(-1), "cuda")
-    _, _, out_off, T, _ = O.Stream(e.desc_bytes, e.bits, e.reuse, e.verts, e.vert_off, e.stats).fields()
+    _, _, out_off, T, _ = so.fields()
     rng = np.random.default_rng(44)
     for v in list(rng.normal(size=(3, 3))) + [np.array([0.0, 0.0, 1.0])]:
         v = (v / np.linalg.norm(v)).astype(np.float32)
-        culled = O.cull(cones, v)
+        culled = O.cull(ocones, v)
         for cfg in CFGS[:3]:
             say(f"[gpu] culled decode caps={caps} view={v} culled={int(culled.sum())}/{culled.size} cfg={cfg}")
             out = torch.full((e.strip_triangles, 3), 0xAA, dtype=torch.uint8, device="cuda")
