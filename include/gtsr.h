@@ -299,7 +299,8 @@ int gtsr_decode_compact(const gtsr_stream* dev, uint32_t format, const uint32_t*
  * sin(largest angle between axis and a normal) + 1e-5, or 2 when that angle
  * is 90 degrees or more (never culled); float64 arithmetic, rounded once to
  * float32, so the result depends only on the triangles and their order.
- * Errors: EINVAL. */
+ * Errors: EINVAL (a kept range decreasing, past triangle_count or longer
+ * than 256 triangles; a triangle or vertex id out of range). */
 int gtsr_meshlet_cones(const uint32_t* indices, uint64_t triangle_count, const float* positions,
                        uint32_t vertex_count, const uint32_t* tri_ids, const uint32_t* kept_off,
                        uint32_t meshlet_count, float* cones);

@@ -82,7 +82,8 @@ struct MeshInfo {
 };
 
 // Splits a mesh's meshlets into items of about `target` strip triangles,
-// coarser if that would need more than max_items items.
+// coarser if that would need more than max_items items.  A mesh that needs
+// more even at the largest target keeps that split; submit refuses it.
 inline void make_cuts(const gtsr_meshlet* ml, uint32_t count, uint32_t target, uint32_t max_items,
                       std::vector<uint32_t>& cuts) {
   uint64_t total = 0;
@@ -97,7 +98,7 @@ inline void make_cuts(const gtsr_meshlet* ml, uint32_t count, uint32_t target, u
       cuts.push_back(end);
       m = end;
     }
-    if (cuts.size() - 1 <= max_items) return;
+    if (cuts.size() - 1 <= max_items || target == 0xFFFFFFFFu) return;
     target = uint32_t(std::min<uint64_t>(0xFFFFFFFFull, std::max<uint64_t>(2ull * target, total / max_items + 256)));
   }
 }

@@ -30,6 +30,8 @@ extern "C" int gtsr_meshlet_cones(const uint32_t* indices, uint64_t triangle_cou
   for (uint32_t m = 0; m < meshlet_count; ++m) {
     if (kept_off[m + 1] < kept_off[m] || kept_off[m + 1] > triangle_count)
       return fail(GTSR_EINVAL, std::string(who) + ": kept_off out of range");
+    if (kept_off[m + 1] - kept_off[m] > kMaxStripTris)   // a meshlet holds at most 256 triangles
+      return fail(GTSR_EINVAL, std::string(who) + ": kept_off gives a meshlet more than 256 triangles");
     double u[256][3];
     uint32_t nu = 0;
     double sx = 0, sy = 0, sz = 0;
@@ -49,7 +51,7 @@ extern "C" int gtsr_meshlet_cones(const uint32_t* indices, uint64_t triangle_cou
       const double bx = p[2][0] - p[0][0], by = p[2][1] - p[0][1], bz = p[2][2] - p[0][2];
       const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
       const double len = std::sqrt(nx * nx + ny * ny + nz * nz);
-      if (len == 0.0 || nu == 256) continue;
+      if (len == 0.0) continue;
       u[nu][0] = nx / len; u[nu][1] = ny / len; u[nu][2] = nz / len;
       sx += u[nu][0]; sy += u[nu][1]; sz += u[nu][2];
       ++nu;

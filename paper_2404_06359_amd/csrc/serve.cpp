@@ -67,7 +67,7 @@ struct gtsr_server {
   std::mutex wake_mu;
   std::condition_variable cv_wake;
   std::thread thread;
-  std::string thread_error;
+  std::string thread_error;              // set by the scheduler thread under mu
 
   explicit gtsr_server(const gtsr_server_params& prm)
       : p(prm), sched(prm.arena, prm.arena_bytes, prm.max_inflight, prm.max_batch, prm.max_items) {}
@@ -123,9 +123,14 @@ bool gtsr_server::admit_and_launch() {
   // The table and work list were written above, before the launch: the kernel
   // reads them from host memory.
   int rc = decode_meshlets_batched(slot.d_table, rows, slot.d_work, items, nullptr, 0, &p.cfg, slot.stream);
-  if (rc == GTSR_OK && hipEventRecord(slot.done, slot.stream) != hipSuccess) rc = GTSR_EHIP;
+  if (rc == GTSR_OK && hipEventRecord(slot.done, slot.stream) != hipSuccess) {
+    // The launch is queued but cannot be tracked: wait for it, so that no
+    // arena range is handed out again while the kernel may still write it.
+    (void)hipStreamSynchronize(slot.stream);
+    rc = GTSR_EHIP;
+  }
   if (rc != GTSR_OK) {
-    // The batch never reached the device: report its requests as failed.
+    // The batch did not complete as tracked work: report its requests as failed.
     {
       std::lock_guard<std::mutex> lk(mu);
       sched.finish(uint32_t(k), rc, now_ns());
@@ -137,6 +142,7 @@ bool gtsr_server::admit_and_launch() {
 
 void gtsr_server::loop() {
   if (hipSetDevice(device) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(mu);
     thread_error = "gtsr_server: cannot select the device";
     return;
   }

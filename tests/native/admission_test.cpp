@@ -248,6 +248,12 @@ void test_make_cuts() {
   CHECK((cuts == std::vector<uint32_t>{0}));
   make_cuts(ml.data(), 10, 1, 100, cuts);   // a meshlet larger than the target is one item
   CHECK(cuts.size() == 11);
+  // more triangles than the largest target holds, one item allowed: the split
+  // stops at that target (two items), which submit then refuses
+  std::vector<gtsr_meshlet> big(65540);
+  for (gtsr_meshlet& m : big) m.tri_count = 65535;
+  make_cuts(big.data(), uint32_t(big.size()), 1u << 31, 1, cuts);
+  CHECK(cuts.size() == 3 && cuts.front() == 0 && cuts.back() == big.size());
 }
 
 // Random operations against a plain model of the policy: every admitted

@@ -312,6 +312,37 @@ def test_library_cones_match_oracle(name, caps):
         np.testing.assert_array_equal(O.cull(cl, v), O.cull(co, v))
 
 
+def test_cone_errors():
+    """Malformed inputs to gtsr_meshlet_cones are refused with EINVAL, never
+    turned into a cone that leaves some triangle out: a kept range past the
+    triangles or longer than a meshlet's 256, a triangle id or a vertex id
+    out of range."""
+    m = meshgen.delaunay(3000, meshgen.rng_for(4, 2))
+    pos = meshgen.vertex_attributes(m)[:, :3].copy()
+    e = P.encode(m.tri, m.nverts, 128, 256)
+    P.meshlet_cones(m.tri, pos, e)
+
+    def cones(tri=m.tri, pos=pos, tri_ids=e.tri_ids, kept_off=e.kept_off, M=e.meshlet_count):
+        tri = np.ascontiguousarray(tri, np.uint32)
+        out = np.zeros((max(M, 1), 4), np.float32)
+        return P.lib().gtsr_meshlet_cones(tri.ctypes.data, tri.shape[0], pos.ctypes.data, pos.shape[0],
+                                          tri_ids.ctypes.data, kept_off.ctypes.data, M, out.ctypes.data)
+
+    assert cones() == P.OK
+    long = np.array([0, 257], np.uint32)            # one meshlet of 257 triangles
+    assert cones(kept_off=long, M=1) == P.EINVAL and "256" in P.lib().gtsr_last_error().decode()
+    assert cones(kept_off=np.array([0, 256], np.uint32), M=1) == P.OK
+    past = e.kept_off.copy()
+    past[-1] = m.ntri + 1
+    assert cones(kept_off=past) == P.EINVAL
+    ids = e.tri_ids.copy()
+    ids[5] = m.ntri
+    assert cones(tri_ids=ids) == P.EINVAL and "triangle id" in P.lib().gtsr_last_error().decode()
+    tri = m.tri.copy()
+    tri[int(e.tri_ids[0]), 1] = pos.shape[0]
+    assert cones(tri=tri) == P.EINVAL and "vertex id" in P.lib().gtsr_last_error().decode()
+
+
 def test_claiming_needs_a_workspace_and_a_batched_decoder():
     """items_per_claim is a batched-decoder knob: other decoders reject it,
     and a claiming launch without a large enough, aligned workspace is
