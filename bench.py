@@ -276,6 +276,42 @@ def build_serve_prototypes(threads: int):
     return protos
 
 
+def build_serve_distinct(count: int, threads: int):
+    """The serving pool as ``count`` distinct meshes (mesh i: triangle count
+    log-uniform in [1e4, 2e7], kind and caps uniform, the same draws as
+    prototype entry i before its size is snapped to a level), generated and
+    encoded on ``threads`` host threads, largest first.  Only what the
+    server reads is kept (descriptors, flag chunks, reuse bytes, counts): the
+    vertex lists and triangle ids of 13 G triangles would fill the host.  The
+    meshes keep their generated vertex numbering: a meshlet's stream holds
+    local indices in first-appearance order and every tie in the encoder's
+    rules is broken by triangle number, so the streams are the bytes the
+    shuffled meshes give (tested), at half the encoding time."""
+    import meshgen
+    import paper_2404_06359_amd as P
+
+    spec = meshgen.workload5_spec(count)
+    order = sorted(range(count), key=lambda i: -spec[i][1])
+    total = float(sum(n for _, n, _ in spec))
+
+    def one(i):
+        m = meshgen.workload5_mesh(i, permute=False)
+        e = P.encode(m.tri, m.nverts, m.max_vertices, m.max_triangles, threads=1)
+        return P.Encoded(e.meshlets, e.bits, e.reuse, np.zeros(0, np.uint32), np.zeros(1, np.uint64), e.stats)
+
+    encs = [None] * count
+    t0, done, tris = time.perf_counter(), 0, 0.0
+    with ThreadPoolExecutor(threads) as ex:
+        for i, e in zip(order, ex.map(one, order)):
+            encs[i] = e
+            done += 1
+            tris += spec[i][1]
+            if done % 100 == 0 or done == count:
+                log(f"[bench] serve pool: {done}/{count} distinct meshes encoded, "
+                    f"{tris / total:.0%} of {total / 1e9:.1f} G triangles, {time.perf_counter() - t0:.0f}s")
+    return encs
+
+
 def run_serve(args, threads):
     """Open-loop serving run: a Poisson stream of decode requests over a
     device-resident pool, admitted by an HBM budget, batched continuously."""
@@ -286,14 +322,20 @@ def run_serve(args, threads):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    protos = build_serve_prototypes(threads)
-    entries = meshgen.workload5_entries(args.pool_meshes)
-    encs = [protos[int(k)] for k in entries]
+    distinct = args.serve_pool == "distinct"
+    if distinct:
+        encs = build_serve_distinct(args.pool_meshes, threads)
+        source = "distinct meshes"
+    else:
+        protos = build_serve_prototypes(threads)
+        entries = meshgen.workload5_entries(args.pool_meshes)
+        encs = [protos[int(k)] for k in entries]
+        source = f"{len(protos)} prototypes"
     pool = P.Pool(encs, device=dev, out=False)
     prep_s = time.perf_counter() - t0
     pool_bytes = int(pool.d_meshlets.numel() + pool.d_bits.numel() + pool.d_reuse.numel())
     in_tris = np.array([e.stats["input_triangles"] for e in encs], np.float64)
-    log(f"[bench] serve prep {prep_s:.1f}s: {len(encs)} pool meshes from {len(protos)} prototypes, "
+    log(f"[bench] serve prep {prep_s:.1f}s: {len(encs)} pool meshes from {source}, "
         f"{in_tris.sum() / 1e9:.2f} G triangles, pool {pool_bytes / 1e9:.2f} GB on the device")
     budget = int(args.hbm_budget_gb * 1e9)
     arena = budget - pool_bytes
@@ -333,10 +375,15 @@ def run_serve(args, threads):
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"serving: Poisson {args.rate:.0f} req/s over a device-resident pool of "
-                               f"{len(encs)} meshes whose entries repeat {len(protos)} encoded prototypes "
-                               f"(2 kinds x 3 caps x {meshgen.SERVE_LEVELS} log-spaced sizes in 1e4-2e7 "
-                               f"triangles), {args.hbm_budget_gb:.0f} GB HBM budget, continuous batching",
+        "config": {"workload": (f"serving: Poisson {args.rate:.0f} req/s over a device-resident pool of "
+                                f"{len(encs)} distinct meshes (grid or sphere patch, 1e4-2e7 triangles each "
+                                f"log-uniform, caps uniform over 32v/64t 64v/126t 128v/256t), "
+                                f"{args.hbm_budget_gb:.0f} GB HBM budget, continuous batching") if distinct else
+                               (f"serving: Poisson {args.rate:.0f} req/s over a device-resident pool of "
+                                f"{len(encs)} meshes whose entries repeat {len(protos)} encoded prototypes "
+                                f"(2 kinds x 3 caps x {meshgen.SERVE_LEVELS} log-spaced sizes in 1e4-2e7 "
+                                f"triangles), {args.hbm_budget_gb:.0f} GB HBM budget, continuous batching"),
+                   "pool": args.serve_pool,
                    "pool_meshes": len(encs), "pool_triangles": int(in_tris.sum()), "pool_bytes": pool_bytes,
                    "arena_bytes": arena, "max_inflight": args.max_inflight, "max_batch": args.max_batch,
                    "target_tris": args.target_tris, "prep_seconds": round(prep_s, 1)},
@@ -524,6 +571,9 @@ def main():
     ap.add_argument("--requests", type=int, default=20000, help="serve: measured requests")
     ap.add_argument("--warm-s", type=float, default=1.0, help="serve: warm-up seconds of arrivals")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: pool + outputs budget")
+    ap.add_argument("--serve-pool", choices=["prototypes", "distinct"], default="prototypes",
+                    help="serve: pool entries repeat 96 encoded prototypes (prepared in seconds), or are "
+                         "distinct meshes (13 G triangles: minutes of host encoding)")
     ap.add_argument("--max-inflight", type=int, default=4, help="serve: batches on the device at once")
     ap.add_argument("--max-batch", type=int, default=256, help="serve: requests per batch")
     ap.add_argument("--meshes", type=int, default=2000)

@@ -249,10 +249,10 @@ def loguniform_int(rng: np.random.Generator, lo: float, hi: float) -> int:
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
 
 
-def grid_for(n: int, rng: np.random.Generator) -> Mesh:
+def grid_for(n: int, rng: np.random.Generator, permute: bool = True) -> Mesh:
     w = max(1, math.ceil(math.sqrt(n / 2)))
     h = max(1, math.ceil(n / (2 * w)))
-    return grid(w, h, rng)
+    return grid(w, h, rng, permute=permute)
 
 
 def workload1() -> Mesh:
@@ -349,14 +349,30 @@ def workload5_entries(count: int = 5000) -> np.ndarray:
     return out
 
 
-def workload5_mesh(i: int, lo: float = 1e4, hi: float = 2e7) -> Mesh:
+def workload5_spec(count: int = 5000, lo: float = 1e4, hi: float = 2e7):
+    """Per-mesh recipe of the serving pool of distinct meshes: ``(kind, n,
+    caps)`` for mesh ``i`` of ``count``, the draws ``workload5_mesh(i)`` makes
+    before it builds the mesh."""
+    out = []
+    for i in range(count):
+        r = rng_for(5, i)
+        n = loguniform_int(r, lo, hi)
+        kind = "grid" if r.integers(2) == 0 else "patch"
+        out.append((kind, n, CAPS[int(r.integers(3))]))
+    return out
+
+
+def workload5_mesh(i: int, lo: float = 1e4, hi: float = 2e7, permute: bool = True) -> Mesh:
     """Mesh ``i`` of the serving pool: like the batched workload, triangle
-    count log-uniform in [lo, hi]."""
+    count log-uniform in [lo, hi].  ``permute=False`` keeps the generator's
+    vertex numbering instead of shuffling it (the shuffle is the last draw, so
+    the triangles are otherwise the same; the encoded streams do not depend on
+    global vertex ids, only the vertex lists do)."""
     r = rng_for(5, i)
     n = loguniform_int(r, lo, hi)
     kind = "grid" if r.integers(2) == 0 else "patch"
     caps = CAPS[int(r.integers(3))]
-    m = grid_for(n, r) if kind == "grid" else sphere_patch(n, r)
+    m = grid_for(n, r, permute) if kind == "grid" else sphere_patch(n, r, permute)
     m.max_vertices, m.max_triangles = caps
     m.meta["target_n"] = n
     return m

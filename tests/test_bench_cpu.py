@@ -2,7 +2,8 @@
 against the per-meshlet figure of the method (flag chunks, reuse bytes,
 descriptors read once; three output bytes per strip triangle written once),
 the rule that reads committed traffic counters only for the kernel source
-they were taken on, and its one-GPU contract."""
+they were taken on, the serving pool of distinct meshes, and its one-GPU
+contract."""
 import os
 import subprocess
 import sys
@@ -60,3 +61,33 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+
+def test_distinct_serving_pool_follows_its_recipe(monkeypatch):
+    """workload5_spec gives the (kind, size, caps) that workload5_mesh builds;
+    the distinct pool holds each mesh's own streams and counts -- the bytes a
+    plain encode of the shuffled mesh gives, though the pool encodes the
+    unshuffled one -- but not its vertex lists or triangle ids."""
+    spec = meshgen.workload5_spec(60)
+    small = [i for i, (_, n, _) in enumerate(spec) if n < 60000][:5]
+    assert len(small) >= 3 and {spec[i][0] for i in small} == {"grid", "patch"}
+    build = meshgen.workload5_mesh
+    meshes = [build(i) for i in small]
+    for i, m in zip(small, meshes):
+        kind, n, caps = spec[i]
+        assert (m.kind, m.meta["target_n"], (m.max_vertices, m.max_triangles)) == (kind, n, caps)
+        plain = build(i, permute=False)
+        assert plain.ntri == m.ntri and not np.array_equal(plain.tri, m.tri)
+    # a pool of just those meshes: mesh j of the patched recipe is mesh small[j]
+    monkeypatch.setattr(meshgen, "workload5_spec", lambda count: [spec[i] for i in small][:count])
+    monkeypatch.setattr(meshgen, "workload5_mesh", lambda j, permute=True: build(small[j], permute=permute))
+    encs = bench.build_serve_distinct(len(small), 2)
+    for e, m in zip(encs, meshes):
+        full = P.encode(m.tri, m.nverts, m.max_vertices, m.max_triangles)
+        np.testing.assert_array_equal(e.meshlets, full.meshlets)
+        np.testing.assert_array_equal(e.bits, full.bits)
+        np.testing.assert_array_equal(e.reuse, full.reuse)
+        assert e.stats["input_triangles"] == full.stats["input_triangles"] == m.ntri
+        assert e.strip_triangles == full.strip_triangles
+        assert e.verts.size == 0 and e.kept_off is None and e.tri_ids is None
