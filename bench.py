@@ -9,7 +9,8 @@ batched launch (autotuned launch shape).  Beside it: the same launch issued
 directly, the same meshes decoded with one plain launch per mesh, the first
 launches after an idle second, a copy kernel with the decode's access pattern
 (the achievable bandwidth), the oracle's sequential decoder timed on the host
-cores, and a short serving run (p50/p99 request latency).
+cores, and a short serving run (p50/p99 request latency over a pool of 5000
+distinct meshes, 13 G triangles, encoded on the host first).
 
 Other workloads (``--workload``): gts (the same meshes as plain GTS
 streams), stress (Delaunay meshes), grid and sphere (one plain launch per
@@ -571,9 +572,10 @@ def main():
     ap.add_argument("--requests", type=int, default=20000, help="serve: measured requests")
     ap.add_argument("--warm-s", type=float, default=1.0, help="serve: warm-up seconds of arrivals")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: pool + outputs budget")
-    ap.add_argument("--serve-pool", choices=["prototypes", "distinct"], default="prototypes",
-                    help="serve: pool entries repeat 96 encoded prototypes (prepared in seconds), or are "
-                         "distinct meshes (13 G triangles: minutes of host encoding)")
+    ap.add_argument("--serve-pool", choices=["distinct", "prototypes"], default="distinct",
+                    help="serve (and the batched run's serving leg): 5000 distinct meshes, 13 G triangles "
+                         "(about three minutes of host encoding), or entries that repeat 96 encoded "
+                         "prototypes (seconds)")
     ap.add_argument("--max-inflight", type=int, default=4, help="serve: batches on the device at once")
     ap.add_argument("--max-batch", type=int, default=256, help="serve: requests per batch")
     ap.add_argument("--meshes", type=int, default=2000)
