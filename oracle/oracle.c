@@ -65,7 +65,10 @@
  *   oracle_cull          per meshlet, the cone around the normalised sum of
  *                        its triangles' unit normals that holds all of them;
  *                        a meshlet is culled for view direction d when the
- *                        whole cone faces away from d.
+ *                        whole cone faces away from d.  The paper fixes no
+ *                        rounding; this one takes the triangles in strip
+ *                        order, each rotated to start at its smallest vertex
+ *                        id, in float64, rounded once to float32.
  *   oracle_compact       Drops the degenerate triangles of the restarts
  *                        (Sec. 4.2: four per restart; they are the only
  *                        triangles with a repeated index) from decoded
