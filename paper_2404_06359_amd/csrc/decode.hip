@@ -781,8 +781,8 @@ __device__ __forceinline__ void decode_items(const gtsr_mesh_entry* __restrict__
 // triangles) and exits; the dispatcher refills freed slots with the next
 // groups, so the blocks of one XCD are decoded roughly in list order.
 // kPlain: every entry holds a plain GTS stream; kTile: the LDS tile (Shape).
-// Eight wavefronts per SIMD (64 VGPRs; the compiler spills one 8-byte value
-// outside the run loop) measured 0.5% faster than seven without the spill.
+// Eight wavefronts per SIMD (64 VGPRs, no scratch) measured 0.5% faster than
+// seven.
 template <bool kPlain, uint32_t kTile>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_decode_batched(
     const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
