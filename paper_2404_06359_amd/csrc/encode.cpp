@@ -669,10 +669,32 @@ extern "C" int encode_meshlets(const uint32_t* indices, uint64_t triangle_count,
     E->vert_off.push_back(0);
     E->kept_off.push_back(0);
     if (T == 0) { *out = E; return ok(); }
+    // Vertex ids in order of first appearance in the triangle list.  No rule
+    // below compares vertex ids: ties go by triangle number, the edge
+    // direction test compares the two ends of one edge (a relabelling flips it
+    // for both of that edge's half-edges alike), and each meshlet renumbers
+    // its vertices by first appearance.  So the streams are the same, but
+    // triangles near each other in the list, which share vertices, get nearby
+    // ids, and the per-vertex arrays are walked with locality instead of at
+    // random.  The vertex lists are mapped back to the caller's ids at the end.
+    std::vector<uint32_t> rel(3ull * T), orig;
+    {
+      std::vector<uint32_t> first(vertex_count, kNone);
+      for (uint64_t i = 0; i < 3ull * T; ++i) {
+        uint32_t& f = first[indices[i]];
+        if (f == kNone) {
+          f = static_cast<uint32_t>(orig.size());
+          orig.push_back(indices[i]);
+        }
+        rel[i] = f;
+      }
+    }
+    const uint32_t* idx = rel.data();
+    const uint32_t V = static_cast<uint32_t>(orig.size());
     Adjacency A;
-    build_adjacency(indices, T, vertex_count, A);
+    build_adjacency(idx, T, V, A);
     Meshlets M;
-    build_meshlets(indices, T, vertex_count, A, max_v, max_t, M);
+    build_meshlets(idx, T, V, A, max_v, max_t, M);
     const uint32_t nm = static_cast<uint32_t>(M.start.size() - 1);
 
     uint32_t threads = params->threads ? params->threads : std::max(1u, std::thread::hardware_concurrency());
@@ -682,8 +704,8 @@ extern "C" int encode_meshlets(const uint32_t* indices, uint64_t triangle_count,
     for (uint32_t i = 0; i < threads; ++i) {
       uint32_t m0 = static_cast<uint32_t>(uint64_t(nm) * i / threads);
       uint32_t m1 = static_cast<uint32_t>(uint64_t(nm) * (i + 1) / threads);
-      if (threads == 1) encode_range(indices, A, M, m0, m1, max_t, exact, pieces[i]);
-      else pool.emplace_back(encode_range, indices, std::cref(A), std::cref(M), m0, m1, max_t, exact,
+      if (threads == 1) encode_range(idx, A, M, m0, m1, max_t, exact, pieces[i]);
+      else pool.emplace_back(encode_range, idx, std::cref(A), std::cref(M), m0, m1, max_t, exact,
                              std::ref(pieces[i]));
     }
     for (auto& th : pool) th.join();
@@ -714,7 +736,7 @@ extern "C" int encode_meshlets(const uint32_t* indices, uint64_t triangle_count,
       }
       if (!P.bits.empty()) std::memcpy(E->bits.data() + chunk0 * 16, P.bits.data(), P.bits.size() * 8);
       E->reuse.insert(E->reuse.end(), P.reuse.begin(), P.reuse.end());
-      E->verts.insert(E->verts.end(), P.verts.begin(), P.verts.end());
+      for (uint32_t v : P.verts) E->verts.push_back(orig[v]);   // back to the caller's vertex ids
       E->tri_ids.insert(E->tri_ids.end(), P.tri_ids.begin(), P.tri_ids.end());
       for (uint32_t v : P.vcount) { vo += v; E->vert_off.push_back(vo); }
       for (uint32_t k : P.kept) { ko += k; E->kept_off.push_back(static_cast<uint32_t>(ko)); }
