@@ -284,10 +284,10 @@ def build_serve_distinct(count: int, threads: int):
     encoded on ``threads`` host threads, largest first.  Only what the
     server reads is kept (descriptors, flag chunks, reuse bytes, counts): the
     vertex lists and triangle ids of 13 G triangles would fill the host.  The
-    meshes keep their generated vertex numbering: a meshlet's stream holds
-    local indices in first-appearance order and every tie in the encoder's
-    rules is broken by triangle number, so the streams are the bytes the
-    shuffled meshes give (tested), at half the encoding time."""
+    meshes keep their generated vertex numbering (no shuffle to draw): a
+    meshlet's stream holds local indices in first-appearance order and every
+    tie in the encoder's rules is broken by triangle number, so the streams
+    are the bytes the shuffled meshes give (tested)."""
     import meshgen
     import paper_2404_06359_amd as P
 
