@@ -400,6 +400,34 @@ def test_check_stream_rejects_corruption():
     assert bad(bits=b) == O.ECORRUPT
 
 
+def test_check_stream_reuse_rule_exhaustive():
+    """Every one-meshlet stream with T_s <= 4, every flag and increment word,
+    reuse bytes 0..6: the checker accepts exactly the streams whose reuse
+    bytes each name a vertex already introduced (Sec. 4.3: a clear increment
+    flag takes the next reuse entry, an index of a vertex seen before), that
+    is, a value below 3 plus the increments before its slot."""
+    import itertools
+
+    checked = accepted = 0
+    for T in range(1, 5):
+        for f in itertools.product((L, R), repeat=T):
+            for gt in itertools.product((0, 1), repeat=T - 1):
+                g = (0,) + gt
+                seen, limits = 3, []
+                for t in range(1, T):
+                    if g[t]:
+                        seen += 1
+                    else:
+                        limits.append(seen)
+                for r in itertools.product(range(7), repeat=len(limits)):
+                    valid = all(x < n for x, n in zip(r, limits))
+                    desc, bits, reuse, ts = pack([(list(f), list(g), list(r))])
+                    assert (O.check_stream(desc, bits, reuse, ts) == 0) == valid, (f, g, r)
+                    checked += 1
+                    accepted += valid
+    assert checked == 8738 and 0 < accepted < checked
+
+
 # ---------------------------------------------------------------- paper values
 
 def _rows(path):
