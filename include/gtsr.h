@@ -572,7 +572,10 @@ typedef struct gtsr_file_mesh {
 } gtsr_file_mesh;
 
 /* Write mesh_count meshes to path (host arrays, read during the call only;
- * kept_off and tri_ids may be NULL).  The file appears whole or not at all
+ * kept_off and tri_ids may be NULL).  Each array must hold the entries its
+ * field's comment names (sizes follow from the counts; the writer cannot
+ * check them).  The streams themselves are written as given: gtsr_file_open
+ * is where they are validated.  The file appears whole or not at all
  * (written under path + ".partial", then renamed).  Errors: EINVAL (null
  * argument or array, bad format), ENOMEM, EIO. */
 int gtsr_file_write(const char* path, const gtsr_file_mesh* meshes, uint32_t mesh_count);

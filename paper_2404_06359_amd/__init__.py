@@ -352,6 +352,13 @@ def save(path: str, encs) -> None:
         parts = [np.ascontiguousarray(x) for x in (e.meshlets, e.bits, e.reuse, e.verts, e.vert_off)]
         kept = None if e.kept_off is None or not e.kept_off.size else np.ascontiguousarray(e.kept_off, np.uint32)
         tids = None if e.tri_ids is None or not e.tri_ids.size else np.ascontiguousarray(e.tri_ids, np.uint32)
+        # the writer takes M + 1 offsets and input_triangles ids on trust: check the arrays hold them
+        M = e.meshlet_count
+        if (parts[4].dtype != np.uint64 or parts[4].size != M + 1 or parts[3].dtype != np.uint32
+                or (kept is not None and kept.size != M + 1)
+                or (tids is not None and tids.size != int(e.stats.get("input_triangles", 0)))):
+            raise ValueError(f"save: mesh {i} lacks its vertex lists, offsets or triangle ids "
+                             "(a stream-only Encoded cannot be saved)")
         keep.append((parts, kept, tids))
         arr[i] = FileMesh(e.format, e.meshlet_count, e.strip_triangles, int(e.stats.get("input_triangles", 0)),
                           int(e.stats.get("restarts", 0)), ptr(parts[0]), ptr(parts[1]), parts[1].nbytes,

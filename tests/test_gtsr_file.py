@@ -169,3 +169,17 @@ def test_write_errors(tmp_path):
     assert L.gtsr_file_write(os.fsencode(str(tmp_path / "b.gtsr")), P.C.byref(m), 1) == P.EINVAL
     assert L.gtsr_file_write(None, None, 0) == P.EINVAL
     assert L.gtsr_file_open(None, None) == P.EINVAL
+
+
+def test_save_refuses_incomplete_meshes(tmp_path):
+    """An Encoded without its vertex lists (as the serving benchmark keeps
+    them: streams and counts only) is refused before the writer reads its
+    offsets."""
+    e = _meshes()[0]
+    slim = P.Encoded(e.meshlets, e.bits, e.reuse, np.zeros(0, np.uint32), np.zeros(1, np.uint64), e.stats)
+    with pytest.raises(ValueError):
+        P.save(str(tmp_path / "slim.gtsr"), [slim])
+    short = P.Encoded(e.meshlets, e.bits, e.reuse, e.verts, e.vert_off, e.stats, e.kept_off, e.tri_ids[:-1])
+    with pytest.raises(ValueError):
+        P.save(str(tmp_path / "short.gtsr"), [short])
+    assert not os.path.exists(tmp_path / "slim.gtsr") and not os.path.exists(tmp_path / "short.gtsr")
