@@ -561,6 +561,9 @@ def decode_compact(ds: DeviceStream, kept_off, out=None, stream=None, cfg=None):
     else:
         kept_dev = kept_off
         total = None
+    # the decoder reads meshlet_count + 1 four-byte offsets
+    if kept_dev.element_size() != 4 or kept_dev.numel() < ds.meshlet_count + 1 or not kept_dev.is_contiguous():
+        raise ValueError(f"decode_compact: kept_off must hold {ds.meshlet_count + 1} contiguous 32-bit offsets")
     if out is None:
         if total is None:   # reads the last offset back from the device (synchronizes)
             total = int(kept_off[-1].item()) if kept_off.numel() else 0

@@ -343,6 +343,20 @@ def test_cone_errors():
     assert cones(tri=tri) == P.EINVAL and "vertex id" in P.lib().gtsr_last_error().decode()
 
 
+def test_decode_compact_refuses_short_offsets():
+    """The compacted decoder reads meshlet_count + 1 offsets: a shorter array
+    is refused by the binding before any device call."""
+    torch = pytest.importorskip("torch")
+    m = meshgen.workload1()
+    e = P.encode(m.tri, m.nverts, 64, 126)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.uint8).reshape(-1).copy())
+    ds = P.DeviceStream(t(e.meshlets), t(e.bits), t(e.reuse), e.meshlet_count, e.strip_triangles)
+    with pytest.raises(ValueError):
+        P.decode_compact(ds, e.kept_off[:-1])
+    with pytest.raises(ValueError):
+        P.decode_compact(ds, torch.zeros(e.meshlet_count + 1, dtype=torch.int16))
+
+
 def test_claiming_needs_a_workspace_and_a_batched_decoder():
     """items_per_claim is a batched-decoder knob: other decoders reject it,
     and a claiming launch without a large enough, aligned workspace is
