@@ -422,6 +422,9 @@ def decode_culled(ds: DeviceStream, cones_dev, view, out=None, stream=None, cfg=
     """``gtsr_decode_culled``: decode the meshlets whose cone does not face away
     from ``view``; culled meshlets' output is left as it was."""
     torch = _torch()
+    # the decoder reads one float4 {axis, cutoff} per meshlet
+    if cones_dev.numel() * cones_dev.element_size() < 16 * ds.meshlet_count or not cones_dev.is_contiguous():
+        raise ValueError(f"decode_culled: cones must hold {ds.meshlet_count} contiguous float4 records")
     if out is None:
         out = torch.zeros((ds.strip_triangles, 3), dtype=torch.uint8, device=ds.meshlets.device)
     d = ds.desc()

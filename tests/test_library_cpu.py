@@ -344,8 +344,9 @@ def test_cone_errors():
 
 
 def test_decode_compact_refuses_short_offsets():
-    """The compacted decoder reads meshlet_count + 1 offsets: a shorter array
-    is refused by the binding before any device call."""
+    """The compacted decoder reads meshlet_count + 1 offsets and the culled
+    decoder one cone per meshlet: shorter arrays are refused by the binding
+    before any device call."""
     torch = pytest.importorskip("torch")
     m = meshgen.workload1()
     e = P.encode(m.tri, m.nverts, 64, 126)
@@ -355,6 +356,9 @@ def test_decode_compact_refuses_short_offsets():
         P.decode_compact(ds, e.kept_off[:-1])
     with pytest.raises(ValueError):
         P.decode_compact(ds, torch.zeros(e.meshlet_count + 1, dtype=torch.int16))
+    # likewise the culled decoder's cones: one float4 per meshlet
+    with pytest.raises(ValueError):
+        P.decode_culled(ds, torch.zeros((e.meshlet_count - 1) * 4, dtype=torch.float32), (0.0, 0.0, 1.0))
 
 
 def test_claiming_needs_a_workspace_and_a_batched_decoder():
