@@ -967,6 +967,9 @@ def quantize_attributes(attrs: np.ndarray, enc: Encoded, bits: int = 16) -> Quan
     M = enc.meshlet_count
     vert_off = np.ascontiguousarray(enc.vert_off, np.uint64)
     verts = np.ascontiguousarray(enc.verts, np.uint32)
+    # the quantizer reads M + 1 offsets and vert_off[M] vertex ids
+    if vert_off.size != M + 1 or verts.size != int(vert_off[-1]):
+        raise ValueError("quantize_attributes: the encoding lacks its vertex lists (stream-only Encoded)")
     origin = np.zeros(n, np.float32)
     delta = np.zeros(n, np.float32)
     lowest = np.zeros((M, n), np.int32)

@@ -356,6 +356,10 @@ def test_decode_compact_refuses_short_offsets():
         P.decode_compact(ds, e.kept_off[:-1])
     with pytest.raises(ValueError):
         P.decode_compact(ds, torch.zeros(e.meshlet_count + 1, dtype=torch.int16))
+    # the host quantizer reads the vertex lists
+    slim = P.Encoded(e.meshlets, e.bits, e.reuse, np.zeros(0, np.uint32), np.zeros(1, np.uint64), e.stats)
+    with pytest.raises(ValueError):
+        P.quantize_attributes(np.zeros((m.nverts, 3), np.float32), slim)
     # likewise the culled decoder's cones: one float4 per meshlet
     with pytest.raises(ValueError):
         P.decode_culled(ds, torch.zeros((e.meshlet_count - 1) * 4, dtype=torch.float32), (0.0, 0.0, 1.0))
