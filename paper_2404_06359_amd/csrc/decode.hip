@@ -609,15 +609,17 @@ __device__ __forceinline__ void store_run(uint8_t* dst, uint32_t shift, uint32_t
                                        0, kOutputPolicy);
 }
 
-// The same five stores store_run issues, all out of range: they write
+// As many stores as store_run issues (five), all out of range: they write
 // nothing.  Issued after the prologue's loads so that both ways into the run
 // loop have five stores after the prefetched loads, which lets the compiler
-// wait for those loads alone.
-__device__ __forceinline__ void store_nothing(uint8_t* any) {
+// wait for those loads alone.  Their data is a register already live (v):
+// constant store data costs registers the decode needs.
+__device__ __forceinline__ void store_nothing(uint8_t* any, uint32_t v) {
   const __amdgpu_buffer_rsrc_t none = buffer(any, 0);
 #pragma unroll
-  for (uint32_t q = 0; q < 4; ++q) store16(none, kOutOfRange + 16 * q, make_uint4(q, 0, 0, 0));
-  __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), none, int(kOutOfRange), 0, kOutputPolicy);
+  for (uint32_t q = 0; q < 4; ++q)
+    __builtin_amdgcn_raw_buffer_store_b32(v, none, int(kOutOfRange + 16 * q), 0, kOutputPolicy);
+  __builtin_amdgcn_raw_buffer_store_b8(uint8_t(v), none, int(kOutOfRange), 0, kOutputPolicy);
 }
 
 // Cones of meshlets [m, min(m + 32, m_end)), one float4 per lane (culling).
@@ -643,7 +645,7 @@ __device__ __forceinline__ void decode_range(const Stream& s, uint32_t m, uint32
   uint4 cdn = kCull ? load_cones(s, mn, m_end, lane) : zero4;
   uint4 bv = load_bits<kPlain>(s, p, lane);
   uint4 rv = load_reuse(s, p, lane);
-  store_nothing(s.out);
+  store_nothing(s.out, lane);
   for (;;) {
     // the tile is free: stage this run's reuse bytes
     if (lane < Shape<kPlain, kTile>::kStage / 16) reinterpret_cast<uint4*>(tile.reuse)[lane] = rv;
@@ -715,6 +717,39 @@ __device__ __forceinline__ void wave_block(uint32_t n, uint32_t wave, uint32_t w
   b1 = min(b0 + share + (q < extra ? 1u : 0u), x1);
 }
 
+// The batched decoder deals the work list to the XCDs in stripes of
+// kStripe items, round-robin (stripe j to XCD j mod 8), and splits each XCD's
+// stripes evenly over its wavefronts.  A list in mesh order mixes meshes of
+// different cost per item; an eighth of it per XCD left the XCDs finishing up
+// to 24 us apart in a 0.55 ms launch, while stripes give each XCD the same
+// mix.  256-item stripes keep each wavefront's block inside one stripe almost
+// always (blocks are a few items), so consecutive items of a mesh still merge.
+constexpr uint32_t kStripe = 256;
+
+// Work items of XCD x: stripes x, x + 8, ... (the list's last stripe may be partial).
+__device__ __forceinline__ uint32_t xcd_items(uint32_t n, uint32_t xcd) {
+  const uint32_t F = n / kStripe, rem = n % kStripe;
+  const uint32_t full = F > xcd ? (F - 1 - xcd) / kXcds + 1 : 0u;
+  return full * kStripe + (F % kXcds == xcd ? rem : 0u);
+}
+
+// The v-th work item of XCD x (v < xcd_items(n, x), so the result is < n).
+__device__ __forceinline__ uint32_t xcd_item(uint32_t v, uint32_t xcd) {
+  return ((v / kStripe) * kXcds + xcd) * kStripe + v % kStripe;
+}
+
+// This wavefront's block [b0, b1) of its XCD's items (indices for xcd_item):
+// equal shares, one more for the first (items mod waves) wavefronts.
+__device__ __forceinline__ void item_block(uint32_t n, uint32_t wave, uint32_t waves, uint32_t& b0, uint32_t& b1,
+                                          uint32_t& xcd) {
+  xcd = blockIdx.x % kXcds;
+  const uint32_t wx = gridDim.x / kXcds * waves;            // waves of this XCD (the grid is a multiple of 8)
+  const uint32_t q = blockIdx.x / kXcds * waves + wave;     // this wave's rank among them
+  const uint32_t len = xcd_items(n, xcd), share = len / wx, extra = len % wx;
+  b0 = min(q * share + min(q, extra), len);
+  b1 = min(b0 + share + (q < extra ? 1u : 0u), len);
+}
+
 // Plain decoder: every wavefront decodes one contiguous block of meshlets.
 // kPlain: plain GTS stream; kCompact: degenerate triangles dropped, kept
 // offsets in `kept`, out_tris counting output triangles.
@@ -740,14 +775,18 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
 // Decodes work items [b0, b1) of the batched work list with the calling
 // wavefront: 64 items at a time, one per lane, merging consecutive items that
 // continue the same mesh into one meshlet range.
-template <bool kPlain, uint32_t kTile>
+// Decodes work items [b0, b1): list positions, or with kStriped the positions
+// of XCD xcd's stripes (xcd_item).
+template <bool kPlain, uint32_t kTile, bool kStriped = false>
 __device__ __forceinline__ void decode_items(const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
                                              const gtsr_work_item* __restrict__ work, uint32_t b0, uint32_t b1,
-                                             RunTile<kPlain, kTile>& tile, const LanePtrs& lp, uint32_t lane) {
+                                             RunTile<kPlain, kTile>& tile, const LanePtrs& lp, uint32_t lane,
+                                             uint32_t xcd = 0) {
   for (uint64_t base = b0; base < b1; base += kWave) {
     const uint32_t cnt = uint32_t(min(b1 - base, uint64_t(kWave)));
     uint4 wi = make_uint4(0xFFFFFFFFu, 0, 0, 0);
-    if (lane < cnt) wi = *reinterpret_cast<const uint4*>(work + base + lane);
+    const uint32_t v = uint32_t(base) + lane;
+    if (lane < cnt) wi = *reinterpret_cast<const uint4*>(work + (kStriped ? xcd_item(v, xcd) : v));
     const uint32_t prev_mesh = __shfl_up(wi.x, 1);
     const uint32_t prev_end = __shfl_up(wi.z, 1);
     // lane continues the item before it: same mesh, starts where it ended
@@ -777,12 +816,12 @@ __device__ __forceinline__ void decode_items(const gtsr_mesh_entry* __restrict__
 }
 
 // Batched decoder, static split: every wavefront of an over-subscribed grid
-// takes one contiguous block of the work list (items are balanced by strip
-// triangles) and exits; the dispatcher refills freed slots with the next
-// groups, so the blocks of one XCD are decoded roughly in list order.
+// takes one block of its XCD's stripes of the work list (items are balanced
+// by strip triangles) and exits; the dispatcher refills freed slots with the
+// next groups, so each XCD decodes its stripes roughly in order.
 // kPlain: every entry holds a plain GTS stream; kTile: the LDS tile (Shape).
-// Eight wavefronts per SIMD (64 VGPRs, no scratch) measured 0.5% faster than
-// seven.
+// Eight wavefronts per SIMD, as many as the LDS tiles admit (47 VGPRs, no
+// scratch; the attribute keeps the compiler within 64).
 template <bool kPlain, uint32_t kTile>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_decode_batched(
     const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
@@ -791,9 +830,9 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) __attribute__((amdgpu_wa
   const uint32_t wave = uniform(threadIdx.x / kWave);
   LanePtrs lp;
   RunTile<kPlain, kTile>& tile = wave_tile<kPlain, kTile>(wave, lane, lp);
-  uint32_t b0, b1;
-  wave_block(work_items, wave, blockDim.x / kWave, b0, b1);
-  decode_items<kPlain, kTile>(table, mesh_count, work, b0, b1, tile, lp, lane);
+  uint32_t b0, b1, xcd;
+  item_block(work_items, wave, blockDim.x / kWave, b0, b1, xcd);
+  decode_items<kPlain, kTile, true>(table, mesh_count, work, b0, b1, tile, lp, lane, xcd);
 }
 
 // Batched decoder, persistent with claimed work: a grid of about the
