@@ -757,7 +757,10 @@ class Pool:
             if items.size else torch.zeros(16, dtype=torch.uint8, device=self.table.device)
         return self
 
-    TUNE_TARGETS = (384, 768, 1536, 3072)
+    # candidate work-item sizes (strip triangles), in order of preference: the
+    # tuner takes the first within 1% of the fastest, and with the XCD stripes
+    # 1536 measured 0.6-1.3% faster than 768 on the mixed batched workload
+    TUNE_TARGETS = (1536, 768, 3072, 384)
 
     def tune_key(self) -> str:
         """The autotune cache key of this pool: device (architecture, CU
