@@ -37,8 +37,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, uint32_
 }
 
 // Steps [q0, q1) of `steps`, one contiguous block per wavefront, XCD-major
-// (workgroups go round-robin over the 8 XCDs), as the decoders split their
-// work lists.
+// (workgroups go round-robin over the 8 XCDs), as the plain decoder splits
+// its meshlets.  Every step costs the same, so these blocks are balanced
+// across the XCDs as they are; the batched decoder deals its work list to
+// the XCDs in stripes only because its items differ in cost.
 __device__ __forceinline__ void calib_block(uint32_t steps, uint32_t& q0, uint32_t& q1) {
   const uint32_t waves = blockDim.x / kWave;
   const uint32_t wave = uint32_t(__builtin_amdgcn_readfirstlane(threadIdx.x / kWave));
