@@ -146,7 +146,8 @@ typedef struct gtsr_launch_cfg {
                                    0 = default, 1280 or 1024 (GTS-Reuse), 1024 (plain GTS);
                                    every other decoder: must be 0 */
   uint32_t items_per_claim;     /* batched decoders: 0 = static split (each wavefront of an
-                                   over-subscribed grid decodes one block of the work list);
+                                   over-subscribed grid decodes one block of its XCD's
+                                   256-item stripes of the work list);
                                    1..1024 = persistent grid (groups_per_cu groups per CU, at
                                    most one wavefront per claim) whose wavefronts claim this
                                    many work items at a time from per-XCD counters kept in
@@ -334,8 +335,10 @@ int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_ou
  *     (default: 256 one-wavefront groups, about nine times what stays
  *     resident, so the dispatcher refills freed slots until the work runs
  *     out; fewer groups when the list has fewer items than that grid has
- *     wavefronts); each wavefront decodes one contiguous block of the work
- *     list and exits.  No atomics; dev_workspace may be NULL.
+ *     wavefronts).  The list is dealt to the 8 XCDs in stripes of 256 items,
+ *     round-robin, so that every XCD gets the same mix of meshes; each
+ *     wavefront decodes one contiguous block of its XCD's stripes and exits.
+ *     No atomics; dev_workspace may be NULL.
  *   k > 0: persistent.  The grid holds groups_per_cu groups per CU (meant
  *     to be about the resident count, e.g. 32 one-wavefront groups), and
  *     each wavefront claims k consecutive items at a time from a counter of
