@@ -342,7 +342,8 @@ int gtsr_decode_meshlets_many(const gtsr_stream* streams, uint8_t* const* dev_ou
  *   k > 0: persistent.  The grid holds groups_per_cu groups per CU (meant
  *     to be about the resident count, e.g. 32 one-wavefront groups), and
  *     each wavefront claims k consecutive items at a time from a counter of
- *     its XCD's eighth of the list until that eighth runs out.  The counters
+ *     its XCD's share of the list (the same stripes) until the share runs
+ *     out.  The counters
  *     live in dev_workspace (device, 4-byte aligned, at least
  *     GTSR_BATCHED_WORKSPACE_BYTES bytes, caller-owned) and are zeroed by a
  *     small kernel enqueued in front of the decode, so calls that share a

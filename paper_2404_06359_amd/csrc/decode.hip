@@ -837,7 +837,8 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) __attribute__((amdgpu_wa
 
 // Batched decoder, persistent with claimed work: a grid of about the
 // resident wavefront count, whose waves claim per_claim consecutive items at
-// a time from a counter of their XCD's share of the list (workgroups go
+// a time from a counter of their XCD's share of the list (its stripes, as
+// in the static split; workgroups go
 // round-robin over the 8 XCDs, so each XCD's waves claim from their own
 // counter, in their own cache lines) until the share runs out.  Each claim's
 // atomic is issued one claim ahead, so its return is in by the time the
@@ -863,13 +864,12 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_batched_cl
   LanePtrs lp;
   RunTile<kPlain, kTile>& tile = wave_tile<kPlain, kTile>(wave, lane, lp);
   const uint32_t xcd = blockIdx.x % kXcds;
-  const uint32_t x0 = uint32_t(uint64_t(work_items) * xcd / kXcds);
-  const uint32_t len = uint32_t(uint64_t(work_items) * (xcd + 1) / kXcds) - x0;
+  const uint32_t len = xcd_items(work_items, xcd);   // this XCD's stripes, as in the static split
   uint32_t* ctr = counters + xcd * kClaimStride;
   uint32_t c = uniform(claim_issue(ctr, per_claim, lane));
   while (c < len) {
     const uint32_t next = claim_issue(ctr, per_claim, lane);
-    decode_items<kPlain, kTile>(table, mesh_count, work, x0 + c, x0 + min(c + per_claim, len), tile, lp, lane);
+    decode_items<kPlain, kTile, true>(table, mesh_count, work, c, min(c + per_claim, len), tile, lp, lane, xcd);
     c = uniform(next);
   }
 }
