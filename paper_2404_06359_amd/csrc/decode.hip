@@ -774,9 +774,8 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void k_decode_plain(
 
 // Decodes work items [b0, b1) of the batched work list with the calling
 // wavefront: 64 items at a time, one per lane, merging consecutive items that
-// continue the same mesh into one meshlet range.
-// Decodes work items [b0, b1): list positions, or with kStriped the positions
-// of XCD xcd's stripes (xcd_item).
+// continue the same mesh into one meshlet range.  [b0, b1) are list positions,
+// or with kStriped positions among XCD xcd's stripes (xcd_item).
 template <bool kPlain, uint32_t kTile, bool kStriped = false>
 __device__ __forceinline__ void decode_items(const gtsr_mesh_entry* __restrict__ table, uint32_t mesh_count,
                                              const gtsr_work_item* __restrict__ work, uint32_t b0, uint32_t b1,
